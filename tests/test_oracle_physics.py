@@ -1,0 +1,297 @@
+"""Pins of the oracle time stepper against what the paper and the mathematics fix.
+
+* equilibrium moment identities (Section III, case 1 of the low-Ma error
+  estimate, Eq. ce.34 and Appendix C): for k <= N and k + N <= Q the discrete
+  moments of f^(0) equal the Maxwellian's exactly;
+* force moments (Eq. nm.4 with the orthogonality Eq. orth): sum F = 0,
+  sum F xi = rho g (used in Eq. nm.10), sum F xi xi = rho (g u + u g), and the
+  third moment of the continuous force term -g.grad_xi f, g_i Pi_jk + perms;
+* collision leaves f^(0) unchanged when g = 0, and a uniform rest state is a
+  fixed point of a full step including the walls (Psi = 1 for uniform density,
+  Section IV.A and Section V);
+* exact mass conservation, per-element balance of absorbed and emitted mass at
+  the walls (Eq. nm.15, discrete reading), momentum injection rho g dt per node
+  and step (Eq. nm.8 with omega (tau + dt/2) = dt);
+* mirror symmetry of the channel and exact reversal under g -> -g;
+* the Navier-Stokes limit of plane Poiseuille flow: curvature -g/nu in the bulk
+  and m * 6 Kn -> 1 (Eq. pf.2) as Kn -> 0 with a roughly constant first-order
+  slip offset (the offset itself is not printed in the paper: parity unpinned);
+* a pure-Python dictionary implementation agrees with the C oracle on tiny grids.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dvm, stepper
+from tests import bruteforce
+
+CASES = [("D2V17", 3), ("D2V37", 4), ("D3V39", 3)]
+
+
+def _maxwell_moment(rho, u, exps):
+    """Moment of rho * N(u, I): prod_d E[(u_d + Z)^a_d]."""
+    out = rho
+    for ud, a in zip(u, exps):
+        s = 0.0
+        for k in range(0, a + 1, 2):
+            s += math.comb(a, k) * ud ** (a - k) * (math.prod(range(k - 1, 0, -2)) if k else 1)
+        out *= s
+    return out
+
+
+def _solver(name, N, **kw):
+    d = dvm.named_dvm(name)
+    defaults = dict(nx=1, ny=8, nz=(8 if d.dim == 3 else 1), kn=0.1, ma=1e-3, N=N)
+    defaults.update(kw)
+    return stepper.OracleSolver(d, **defaults)
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_equilibrium_moment_identities(oracle_lib, name, N):
+    s = _solver(name, N)
+    d = s.dvm
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        rho = 1.0 + 0.2 * rng.random()
+        u = 0.15 * rng.normal(size=d.dim)
+        feq = s.equilibrium(rho, u)
+        xi = d.xi
+        for k in range(0, N + 1):
+            if k + N > d.Q:
+                continue
+            for exps in itertools.product(range(k + 1), repeat=d.dim):
+                if sum(exps) != k:
+                    continue
+                got = float(np.sum(feq * np.prod(xi ** np.array(exps), axis=1)))
+                want = _maxwell_moment(rho, u, exps)
+                assert abs(got - want) < 2e-14 * max(1.0, abs(want))
+        # order N+1 is not captured by the truncated expansion
+        big = int(np.argmax(np.abs(u)))
+        exps = tuple(N + 1 if dd == big else 0 for dd in range(d.dim))
+        got = float(np.sum(feq * xi[:, big] ** (N + 1)))
+        assert abs(got - _maxwell_moment(rho, u, exps)) > 1e-8
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_tensor_equilibrium_matches_scalar_recurrence(oracle_lib, name, N):
+    s = _solver(name, N)
+    d = s.dvm
+    rng = np.random.default_rng(3)
+    rho = 1.07
+    u = 0.05 * rng.normal(size=d.dim)
+    feq = s.equilibrium(rho, u)
+    ref = [bruteforce.equilibrium(d.weights[a], d.xi[a], rho, u, N) for a in range(d.V)]
+    np.testing.assert_allclose(feq, ref, rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_force_moments(oracle_lib, name, N):
+    s = _solver(name, N)
+    d = s.dvm
+    g = np.array(s.params.g[: d.dim]) * 50.0 + np.array([0.0, 0.01, 0.02][: d.dim])
+    s._p.g[0], s._p.g[1], s._p.g[2] = (list(g) + [0.0])[:3]
+    rng = np.random.default_rng(5)
+    rho = 0.93
+    u = 0.05 * rng.normal(size=d.dim)
+    A = rng.normal(size=(d.dim, d.dim))
+    Pi = rho * np.eye(d.dim) + 0.1 * (A + A.T)
+    F = s.force(rho, u, Pi)
+    xi = d.xi
+    assert abs(F.sum()) < 1e-16
+    np.testing.assert_allclose(xi.T @ F, rho * g, rtol=0, atol=1e-16)
+    M2 = np.einsum("a,ai,aj->ij", F, xi, xi)
+    np.testing.assert_allclose(M2, rho * (np.outer(g, u) + np.outer(u, g)), rtol=0, atol=1e-16)
+    M3 = np.einsum("a,ai,aj,ak->ijk", F, xi, xi, xi)
+    want = (np.einsum("i,jk->ijk", g, Pi) + np.einsum("j,ik->ijk", g, Pi)
+            + np.einsum("k,ij->ijk", g, Pi))
+    np.testing.assert_allclose(M3, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_collision_fixed_point_without_force(oracle_lib, name, N):
+    s = _solver(name, N, g=(0.0, 0.0, 0.0))
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        rho = 1.0 + 0.1 * rng.random()
+        u = 0.01 * rng.normal(size=s.dvm.dim)
+        f0 = s.equilibrium(rho, u)
+        out = s.collide_node(f0)
+        np.testing.assert_allclose(out, f0, rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_uniform_rest_state_is_fixed_point_with_walls(oracle_lib, name, N):
+    kw = dict(nx=3, ny=7, g=(0.0, 0.0, 0.0))
+    if name == "D3V39":
+        kw.update(nz=6, walls_z=True)
+    s = _solver(name, N, **kw).init(rho=np.full(3 * 7 * (6 if name == "D3V39" else 1), 1.3))
+    f0 = s.f.copy()
+    s.run(3)
+    np.testing.assert_allclose(s.f, f0, rtol=3e-15, atol=0)
+
+
+def _random_state(s, seed, amp=1e-3):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + amp * rng.standard_normal(s.nodes)
+    u = np.zeros((s.nodes, 3))
+    u[:, : s.dim] = amp * rng.standard_normal((s.nodes, s.dim))
+    return s.init(rho=rho, u=u)
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_mass_conservation(oracle_lib, name, N):
+    kw = dict(nx=4, ny=9)
+    if name == "D3V39":
+        kw.update(nz=7, walls_z=True)
+    s = _random_state(_solver(name, N, **kw), 1)
+    m0 = s.f.sum()
+    s.run(300)
+    # rounding only: a random walk of ~1e-16 per step
+    assert abs(s.f.sum() - m0) / m0 < 5e-14
+
+
+def test_mass_conservation_config1_long(oracle_lib):
+    s = _random_state(_solver("D2V17", 3, nx=1, ny=40), 2)
+    m0 = s.f.sum()
+    s.run(20000)
+    assert abs(s.f.sum() - m0) / m0 < 1e-13
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_wall_balance_per_element(oracle_lib, name, N):
+    """Absorbed mass per element equals emitted mass per element, checked by an
+    independent enumeration of the stream output."""
+    kw = dict(nx=5, ny=7)
+    if name == "D3V39":
+        kw.update(nz=6, walls_z=True)
+    s = _random_state(_solver(name, N, **kw), 4, amp=1e-2)
+    s.run(2)
+    A, Dn = s.wall_balance()
+    pre = s.stream()
+    d = s.dvm
+    nx, ny, nz = s.nx, s.ny, s.nz
+    emitted = np.zeros_like(A)
+    shape = (nz, ny, nx)
+    for k, j, i in itertools.product(range(nz), range(ny), range(nx)):
+        n = np.ravel_multi_index((k, j, i), shape)
+        for a in range(d.V):
+            e = list(d.velocities[a]) + [0] * (3 - d.dim)
+            js, ks = j - e[1], k - e[2]
+            oy = not (0 <= js < ny)
+            oz = s.walls_z and not (0 <= ks < nz)
+            if not (oy or oz):
+                continue
+            assert Dn.sum() > 0
+            # first face crossed going outward from the node along -e (ties: y);
+            # element = the node's own cell on that face
+            if oy and oz:
+                ty = ((ny - 0.5 if -e[1] > 0 else -0.5) - j) / -e[1]
+                tz = ((nz - 0.5 if -e[2] > 0 else -0.5) - k) / -e[2]
+                use_z = tz < ty
+            else:
+                use_z = oz
+            if use_z:
+                face = 2 if e[2] > 0 else 3
+                el = j * nx + i
+            else:
+                face = 0 if e[1] > 0 else 1
+                el = k * nx + i
+            emitted[face, el] += pre[n, a]
+    np.testing.assert_allclose(emitted, A, rtol=1e-13, atol=1e-15)
+    # every element with absorbed mass also has emitting slots
+    assert np.all(Dn[A > 0] > 0)
+    # streaming alone conserves mass
+    assert abs(pre.sum() - s.f.sum()) < 1e-13 * s.f.sum()
+
+
+@pytest.mark.parametrize("name,N", CASES)
+def test_momentum_injection_per_node(oracle_lib, name, N):
+    kw = dict(nx=2, ny=5)
+    if name == "D3V39":
+        kw.update(nz=4, walls_z=True)
+    s = _random_state(_solver(name, N, **kw), 6, amp=1e-2)
+    pre = s.stream()
+    post = s.collide(pre)
+    rho = pre.sum(axis=1)
+    dj = (post - pre) @ s.dvm.xi
+    want = rho[:, None] * np.array(s.params.g[: s.dim])[None, :] * s.params.dt
+    # (post - pre) . xi cancels O(0.1) populations: rounding ~1e-17 absolute
+    np.testing.assert_allclose(dj, want, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(post.sum(axis=1), rho, rtol=1e-15)
+
+
+def test_channel_symmetry_and_force_reversal(oracle_lib):
+    s1 = _solver("D2V37", 4, nx=1, ny=12).init().run(400)
+    o1 = s1.observe()
+    ux = o1["u"][:, 0, 0]
+    assert np.max(np.abs(ux - ux[::-1])) < 1e-12 * np.max(np.abs(ux))
+    g = s1.params.g
+    s2 = _solver("D2V37", 4, nx=1, ny=12, g=(-g[0], 0.0, 0.0)).init().run(400)
+    o2 = s2.observe()
+    np.testing.assert_allclose(o2["u"][:, 0, 0], -ux, rtol=1e-12, atol=0)
+
+
+def test_x_invariance_of_uniform_start(oracle_lib):
+    a = _solver("D2V17", 3, nx=1, ny=10).init().run(50).observe()
+    b = _solver("D2V17", 3, nx=3, ny=10).init().run(50).observe()
+    for i in range(3):
+        np.testing.assert_allclose(b["u"][:, i, 0], a["u"][:, 0, 0], rtol=1e-14)
+
+
+@pytest.mark.slow
+def test_navier_stokes_limit(oracle_lib):
+    """Bulk curvature -g/nu and m * 6 Kn -> 1 with an O(1) slip offset."""
+    offsets, ratios = [], []
+    for kn in (0.02, 0.01, 0.005):
+        s = _solver("D2V17", 3, nx=1, ny=40, kn=kn).init()
+        p = s.params
+        s.run(int(14 / (math.pi ** 2 * p.tau) / p.dt))
+        o = s.observe()
+        ux = o["u"][:, 0, 0]
+        y = (np.arange(40) + 0.5) / 40 - 0.5
+        mid = np.abs(y) < 0.25
+        curv = np.polyfit(y[mid], ux[mid], 2)[0]
+        # NS: nu u'' = -g  ->  u = const - g y^2 / (2 nu); g / (2 nu) = 4 Ma
+        assert abs(curv / (-p.g[0] / (2 * p.tau)) - 1) < 1e-4
+        offsets.append(o["mdot"] - 1 / (6 * kn))
+        ratios.append(o["mdot"] * 6 * kn)
+    assert ratios[0] > ratios[1] > ratios[2] > 1.0
+    assert ratios[2] < 1.05
+    assert max(offsets) - min(offsets) < 0.15 * np.mean(offsets)
+
+
+def test_psi_close_to_one_at_steady_state(oracle_lib):
+    s = _solver("D2V17", 3, nx=1, ny=20, kn=0.1).init().run(6000)
+    A, Dn = s.wall_balance()
+    o = s.observe()
+    rho_first = o["rho"][0, 0]
+    for face in (0, 1):
+        psi = A[face, 0] / Dn[face, 0] / rho_first
+        assert abs(psi - 1) < 1e-6          # 1 + O(Ma^2), Ma = 1e-3
+    uy = o["u"][:, 0, 1]
+    assert np.max(np.abs(uy)) < 1e-9
+
+
+@pytest.mark.parametrize("name,N", [("D2V17", 3), ("D2V37", 4)])
+def test_bruteforce_python_matches_c_oracle(oracle_lib, name, N):
+    nx, ny = 3, 6
+    s = _random_state(_solver(name, N, nx=nx, ny=ny, ma=5e-2), 8, amp=2e-2)
+    d = s.dvm
+    vels = [tuple(int(v) for v in e) for e in d.velocities]
+    f = {}
+    for j in range(ny):
+        for i in range(nx):
+            n = j * nx + i
+            for a, e in enumerate(vels):
+                f[(i, j, e)] = s.f[n, a]
+    p = s.params
+    for _ in range(3):
+        f = bruteforce.step(f, vels, list(d.weights), d.c, nx, ny, N, p.tau, p.dt, p.g[:2])
+    s.run(3)
+    for j in range(ny):
+        for i in range(nx):
+            n = j * nx + i
+            for a, e in enumerate(vels):
+                assert abs(f[(i, j, e)] - s.f[n, a]) < 1e-15
