@@ -1,0 +1,175 @@
+/*
+ * lbmdvm: high-order lattice Boltzmann (discrete velocity model) channel and
+ * duct solver for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Feuchter & Schleifenbaum, "High-order lattice
+ * Boltzmann models for wall-bounded flows at finite Knudsen numbers"
+ * (arXiv:1510.08886): an on-lattice DVM for the Boltzmann-BGK equation with an
+ * order-N Hermite equilibrium, a Hermite-expanded body force, the trapezoidal
+ * (modified population) time integration, and the diffuse Maxwell wall on the
+ * unknown populations of half-way walls.
+ *
+ * Conventions
+ *   - Every call returns an int: LBM_OK (0) or a negative LBM_E_* code.
+ *     lbm_last_error() returns a thread-local message for the last failure.
+ *   - The caller owns every device buffer and the HIP stream. The library never
+ *     allocates or frees caller memory; it owns only opaque host handles.
+ *     "dev" pointers are device pointers, "host" pointers are host pointers.
+ *   - A handle is single-threaded; distinct handles may run concurrently on
+ *     distinct streams. No exception crosses this interface.
+ *   - Units follow the paper: channel width l0 = 1, isothermal sound speed
+ *     c0 = 1, theta = 1. Nodes sit at y_j = (j + 1/2) dx, dx = 1/ny; walls are
+ *     half a spacing outside the first and last node (y = 0 and y = 1).
+ *   - 2D problems have walls normal to y and a periodic x; 3D ducts have walls
+ *     normal to y and z and a periodic x.
+ */
+#ifndef LBMDVM_H
+#define LBMDVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_E_INVALID (-1)         /* bad argument or inconsistent sizes */
+#define LBM_E_UNSUPPORTED (-2)     /* valid request the library has no kernel for */
+#define LBM_E_NO_MEMORY (-3)       /* caller buffer / pool too small */
+#define LBM_E_QUADRATURE (-4)      /* velocity set is not a quadrature of the stated order */
+#define LBM_E_DEVICE (-5)          /* HIP runtime error */
+#define LBM_E_NOT_CONVERGED (-6)   /* step limit reached before the tolerance */
+
+typedef struct lbm_dvm lbm_dvm_t;
+typedef struct lbm_solver lbm_solver_t;
+typedef struct lbm_batch lbm_batch_t;
+
+/* Population storage. The collision is FP64 for LBM_F64 and FP32 otherwise;
+ * the wall-flux balance and the mass-flux reductions are FP64 in every mode.
+ * Every post-collision population is rounded to the storage type every step. */
+enum lbm_storage {
+    LBM_F64 = 0,     /* fbar in double */
+    LBM_F32 = 1,     /* fbar as the FP32 deviation fbar - w rho0 (round to nearest) */
+    LBM_F16DEV = 2,  /* half-precision scaled deviation fbar / (w rho0) - 1, rounded
+                        stochastically with a counter-based hash of (node, velocity,
+                        step): unbiased, deterministic and reproducible */
+    LBM_F32RAW = 3   /* fbar itself in FP32 (round to nearest); its rounding step is
+                        ~6e-8 of w rho0, so slow relaxations stagnate early */
+};
+
+/* Problem statement (Section V / VI of the paper). */
+typedef struct {
+    int dim;              /* 2: channel (walls at y); 3: duct (walls at y and z) */
+    int nx, ny, nz;       /* nodes; nx periodic; nz ignored (1) in 2D */
+    double kn;            /* Knudsen number; tau = kn * sqrt(2/pi) (Eq. nm.13) */
+    double ma;            /* used when g_set == 0: g = 8 tau ma along x, i.e. the
+                             Navier-Stokes no-slip centreline speed is ma */
+    int g_set;            /* 1: take g[] as given */
+    double g[3];          /* body-force acceleration (Eq. nm.4); g.n must be 0 */
+    int hermite_order;    /* N of the equilibrium (Eq. equi.hermite), 2..(Q+1)/2 */
+    double accommodation; /* 1 = fully diffuse Maxwell wall (only value supported) */
+    double rho0;          /* reference density (deviation storage, initial state) */
+    int storage;          /* enum lbm_storage */
+} lbm_problem_t;
+
+/* Derived per-solve scalars. */
+typedef struct {
+    double tau;           /* relaxation time, Eq. nm.13 */
+    double dt;            /* time step 1 / (c * ny): xi dt = e dx */
+    double omega;         /* dt / (tau + dt/2), Eq. nm.8 */
+    double g[3];          /* body force */
+    double u_c;           /* centreline speed g / (8 tau) used to normalise mass flow */
+    double mdot_scale;    /* 1 / (4 u_c kn): mdot = mdot_scale * <u_x> (Eq. pf.1) */
+    int V;                /* velocities */
+    int halo;             /* max |e_i| over the velocity set */
+} lbm_params_t;
+
+const char *lbm_last_error(void);
+
+/* ---- discrete velocity models (Section II) -------------------------------- */
+
+/* Solve the weights of a minimal DVM: the velocity groups are the signed
+ * permutations of the n_groups generators gen[n_groups * dim] (Eq. wdach); the
+ * moment conditions to degree Q (Eqs. genQua / orth) admit a solution only at
+ * isolated lattice speeds c* (Eq. dimker). Returns the smallest c* in
+ * [c_lo, c_hi] whose group weights are all positive, in *c_out, the weights in
+ * w_group_out[n_groups] and the velocity count in *n_vel_out (any output may be
+ * NULL). LBM_E_QUADRATURE if there is none. Host only. */
+int lbm_dvm_solve(int dim, int n_groups, const int32_t *gen, int Q, double c_lo,
+                  double c_hi, double *c_out, double *w_group_out, int *n_vel_out);
+
+/* Expand the groups into a velocity set with weights w_group (host arrays) and
+ * lattice speed c, and check that it integrates every monomial of degree <= Q
+ * exactly (relative tolerance 1e-12 against the Gaussian moment); otherwise
+ * LBM_E_QUADRATURE. The library orders the velocities as rest velocities first,
+ * then pairs (e, -e). */
+int lbm_dvm_create(int dim, int n_groups, const int32_t *gen, const double *w_group,
+                   double c, int Q, lbm_dvm_t **out);
+int lbm_dvm_destroy(lbm_dvm_t *dvm);
+
+/* Velocity count, integer velocities vel[V * dim] (xi = c * vel), weights w[V]
+ * and lattice speed; vel, w and c may be NULL (size query). Host arrays. */
+int lbm_dvm_info(const lbm_dvm_t *dvm, int *V, int32_t *vel, double *w, double *c);
+
+/* ---- solver --------------------------------------------------------------- */
+
+/* Derived scalars for a problem (pure host). */
+int lbm_params(const lbm_dvm_t *dvm, const lbm_problem_t *prob, lbm_params_t *out);
+
+/* Bytes the caller must provide: each of the two population buffers
+ * (*pop_bytes) and the scratch buffer (*scratch_bytes). */
+int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, size_t *pop_bytes,
+                    size_t *scratch_bytes);
+
+/* Create a solver over caller device buffers pop_a, pop_b (ping-pong
+ * populations, each >= pop_bytes) and scratch (>= scratch_bytes), all aligned to
+ * 256 bytes, on the HIP stream `stream` (hipStream_t; NULL = default stream).
+ * Validation (LBM_E_INVALID): ny (and nz in 3D) >= the largest |e_n|;
+ * 2 <= N <= (Q+1)/2; kn > 0; g.n = 0; sizes positive. accommodation != 1 gives
+ * LBM_E_UNSUPPORTED, as does a velocity count without a compiled kernel. */
+int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
+                      void *pop_b, void *scratch, size_t scratch_bytes, void *stream,
+                      lbm_solver_t **out);
+int lbm_solver_destroy(lbm_solver_t *s);
+
+/* Set the post-collision state to the equilibrium f^(0)(rho, u) of Eq.
+ * equi.hermite at every node. rho_dev[nodes] and u_dev[nodes * 3] are device
+ * FP64 arrays in node order ((k * ny + j) * nx + i); NULL means rho0 and rest. */
+int lbm_init_equilibrium(lbm_solver_t *s, const double *rho_dev, const double *u_dev);
+
+/* Enqueue nsteps fused stream + wall + collide steps (Eq. nm.8); asynchronous. */
+int lbm_run(lbm_solver_t *s, int64_t nsteps);
+
+/* Run until |mdot_k - mdot_{k-1}| / |mdot_k| < tol, where mdot is evaluated
+ * every check_every steps; blocking (synchronises the stream at each check).
+ * *steps = steps done, *mdot = last mass flow. LBM_E_NOT_CONVERGED if
+ * max_steps is reached first. */
+int lbm_run_to_tol(lbm_solver_t *s, double tol, int check_every, int64_t max_steps,
+                   int64_t *steps, double *mdot);
+
+/* Moments of the current state after streaming (the pre-collision state of the
+ * next step, Eq. nm.10): rho_dev[nodes], u_dev[nodes * 3] (device FP64, may be
+ * NULL); *mdot_host = normalised mass flow (Eq. pf.1), *mass_host = total mass
+ * (host, may be NULL). Blocking when a host output is requested. */
+int lbm_observe(lbm_solver_t *s, double *rho_dev, double *u_dev, double *mdot_host,
+                double *mass_host);
+
+/* Post-collision populations as FP64 [alpha][z][y][x] (device array of
+ * V * nodes doubles, alpha in lbm_dvm_info order). */
+int lbm_export_populations(lbm_solver_t *s, double *out_dev);
+
+/* Replace the state by FP64 [alpha][z][y][x] populations (checkpoint resume);
+ * rounds to the storage type (to nearest: an exported state re-imports
+ * bit-exactly) and rebuilds the wall-flux balance. The step counter, which keys
+ * stochastic rounding, is kept, so export, import and run continue a run
+ * bit-exactly. */
+int lbm_import_populations(lbm_solver_t *s, const double *in_dev);
+
+/* Steps taken since the last init/import. */
+int lbm_solver_steps(const lbm_solver_t *s, int64_t *steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMDVM_H */

@@ -1,0 +1,387 @@
+// C ABI of the single-solve path: parameters (Section V of the paper), caller
+// buffers, and the launch sequence of the fused step kernel.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t plane_of(int64_t nodes) { return (nodes + 63) / 64 * 64; }
+
+size_t storage_bytes(int s) {
+    switch (s) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16DEV: return 2;
+        case LBM_F32RAW: return 4;
+        default: return 0;
+    }
+}
+
+int64_t nodes_of(const lbm_problem_t &p) {
+    return (int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
+}
+
+// wall elements per face: 2D y-walls have nx; a duct's y-faces nx*nz, z-faces nx*ny
+int64_t face_elems(const lbm_problem_t &p) {
+    if (p.dim == 2) return p.nx;
+    return std::max<int64_t>((int64_t)p.nx * p.nz, (int64_t)p.nx * p.ny);
+}
+
+struct Layout {
+    size_t pop_bytes = 0;
+    size_t apart_bytes = 0;     // one copy of the wall partials
+    size_t partial_bytes = 0;   // observation block partials
+    size_t off_a0 = 0, off_a1 = 0, off_partial = 0, off_out = 0, scratch_bytes = 0;
+};
+
+Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
+    Layout L;
+    const int64_t nodes = nodes_of(p);
+    L.pop_bytes = align_up((size_t)d.V * plane_of(nodes) * storage_bytes(p.storage));
+    L.apart_bytes = align_up(sizeof(double) * 4 * std::max(1, d.halo) * face_elems(p));
+    L.partial_bytes = align_up(sizeof(double) * 2 * observe_blocks(nodes));
+    L.off_a0 = 0;
+    L.off_a1 = L.apart_bytes;
+    L.off_partial = 2 * L.apart_bytes;
+    L.off_out = L.off_partial + L.partial_bytes;
+    L.scratch_bytes = L.off_out + align_up(2 * sizeof(double));
+    return L;
+}
+
+int validate(const Dvm &d, const lbm_problem_t &p) {
+    if (p.dim != d.dim) return fail(LBM_E_INVALID, "problem dim differs from the DVM's");
+    if (p.nx < 1 || p.ny < 1 || (p.dim == 3 && p.nz < 1)) return fail(LBM_E_INVALID, "sizes must be positive");
+    int hn = 0;
+    for (int v = 0; v < d.V; ++v) {
+        hn = std::max(hn, std::abs(d.vel[3 * v + 1]));
+        if (p.dim == 3) hn = std::max(hn, std::abs(d.vel[3 * v + 2]));
+    }
+    if (p.ny < hn || (p.dim == 3 && p.nz < hn))
+        return fail(LBM_E_INVALID, "ny (and nz) must be at least the largest wall-normal |e|");
+    if (p.hermite_order < 2 || p.hermite_order > (d.Q + 1) / 2)
+        return fail(LBM_E_INVALID, "hermite order must satisfy 2 <= N <= (Q+1)/2");
+    if (!(p.kn > 0)) return fail(LBM_E_INVALID, "kn must be positive");
+    if (p.g_set && (p.g[1] != 0.0 || (p.dim == 3 && p.g[2] != 0.0)))
+        return fail(LBM_E_INVALID, "the body force must be parallel to the walls (g.n = 0)");
+    if (!p.g_set && !(std::isfinite(p.ma))) return fail(LBM_E_INVALID, "ma must be finite");
+    if (!(p.rho0 > 0)) return fail(LBM_E_INVALID, "rho0 must be positive");
+    if (storage_bytes(p.storage) == 0) return fail(LBM_E_INVALID, "unknown storage");
+    if (p.accommodation != 1.0)
+        return fail(LBM_E_UNSUPPORTED, "only the fully diffuse Maxwell wall (accommodation 1) is implemented");
+    if (d.V / 2 > kMaxPairs) return fail(LBM_E_UNSUPPORTED, "velocity set too large for the kernel tables");
+    return LBM_OK;
+}
+
+void derive(const Dvm &d, const lbm_problem_t &p, lbm_params_t &o) {
+    std::memset(&o, 0, sizeof(o));
+    o.tau = p.kn * std::sqrt(2.0 / M_PI);   // Eq. nm.13 with tau = nu (Eq. nm.11)
+    o.dt = 1.0 / (d.c * p.ny);              // xi dt = e dx, dx = l0 / ny
+    o.omega = o.dt / (o.tau + 0.5 * o.dt);  // Eq. nm.8
+    if (p.g_set) {
+        for (int k = 0; k < 3; ++k) o.g[k] = p.g[k];
+    } else {
+        o.g[0] = 8.0 * o.tau * p.ma;         // NS centreline g l0^2 / (8 nu) = ma
+    }
+    o.u_c = o.g[0] != 0.0 ? o.g[0] / (8.0 * o.tau) : (p.ma != 0.0 ? p.ma : 1.0);
+    o.mdot_scale = 1.0 / (4.0 * o.u_c * p.kn);  // Eq. pf.1
+    o.V = d.V;
+    o.halo = d.halo;
+}
+
+}  // namespace
+
+struct Solver {
+    Dvm dvm;
+    lbm_problem_t prob{};
+    lbm_params_t par{};
+    Storage st = Storage::F64;
+    const Launch *L = nullptr;
+    void *pop[2] = {nullptr, nullptr};
+    double *apart[2] = {nullptr, nullptr};
+    double *partial = nullptr;
+    double *out = nullptr;
+    int cur = 0;
+    hipStream_t stream = nullptr;
+    alignas(16) unsigned char tab[sizeof(PairTable<double>)];
+    alignas(16) unsigned char sc[sizeof(StepScalars<double>)];
+    int64_t nodes = 0;
+    int64_t steps = 0;
+    int xcd_remap = 1;
+};
+
+template <typename R>
+static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t &par, void *tab,
+                        void *sc) {
+    auto *t = new (tab) PairTable<R>();
+    auto *s = new (sc) StepScalars<R>();
+    std::memset(tab, 0, sizeof(PairTable<R>));
+    std::memset(sc, 0, sizeof(StepScalars<R>));
+    const double rho0 = p.rho0;
+    const int nx = p.nx;
+    auto shape = [&](int v) {
+        double gx = 0;
+        for (int k = 0; k < 3; ++k) gx += par.g[k] * d.c * d.vel[3 * v + k];
+        return d.w[v] * (1.0 - 0.5 * par.dt * gx);
+    };
+    if (d.n_rest) {
+        t->w0 = (R)d.w[0];
+        t->wr00 = (R)(d.w[0] * rho0);
+        t->inv_wr00 = (R)(1.0 / (d.w[0] * rho0));
+        t->wrd0 = d.w[0] * rho0;
+        t->shape0 = shape(0);
+    }
+    const int np = d.V / 2;
+    for (int q = 0; q < np; ++q) {
+        const int v = d.n_rest + 2 * q;
+        const int *e = &d.vel[3 * v];
+        double xi[3];
+        for (int k = 0; k < 3; ++k) xi[k] = d.c * e[k];
+        for (int k = 0; k < 3; ++k) t->xi[q][k] = (R)xi[k];
+        t->qq[q][0] = (R)(xi[0] * xi[0]);
+        t->qq[q][1] = (R)(xi[1] * xi[1]);
+        t->qq[q][2] = (R)(xi[2] * xi[2]);
+        t->qq[q][3] = (R)(xi[0] * xi[1]);
+        t->qq[q][4] = (R)(xi[0] * xi[2]);
+        t->qq[q][5] = (R)(xi[1] * xi[2]);
+        t->w[q] = (R)d.w[v];
+        t->wr0[q] = (R)(d.w[v] * rho0);
+        t->inv_wr0[q] = (R)(1.0 / (d.w[v] * rho0));
+        t->wrd[q] = d.w[v] * rho0;
+        t->shape_p[q] = shape(v);
+        t->shape_m[q] = shape(v + 1);
+        t->ex[q] = e[0];
+        t->ey[q] = e[1];
+        t->ez[q] = e[2];
+        t->exm[q] = ((e[0] % nx) + nx) % nx;
+        t->exmn[q] = ((-e[0] % nx) + nx) % nx;
+    }
+    s->rho0 = (R)rho0;
+    s->rho0d = rho0;
+    s->tau = (R)par.tau;
+    s->omega = (R)par.omega;
+    const double h = par.dt / (2.0 * par.tau);
+    s->h = (R)h;
+    s->inv1h = (R)(1.0 / (1.0 + h));
+    for (int k = 0; k < 3; ++k) {
+        s->g[k] = (R)par.g[k];
+        s->half_dt_g[k] = (R)(0.5 * par.dt * par.g[k]);
+    }
+    double fact = 1.0;
+    for (int k = 0; k < 6; ++k) {
+        if (k > 0) fact *= k;
+        s->cn[k] = k <= p.hermite_order ? (R)(1.0 / fact) : (R)0;
+    }
+    // D(e): emitted slots per element; uniform along each face of a channel
+    double D[4] = {0, 0, 0, 0};
+    for (int v = 0; v < d.V; ++v) {
+        const int ey = d.vel[3 * v + 1];
+        if (ey > 0) D[0] += ey * shape(v);
+        if (ey < 0) D[1] += -ey * shape(v);
+        if (d.dim == 3) {
+            const int ez = d.vel[3 * v + 2];
+            if (ez > 0) D[2] += ez * shape(v);
+            if (ez < 0) D[3] += -ez * shape(v);
+        }
+    }
+    for (int k = 0; k < 4; ++k) s->invD[k] = D[k] > 0 ? 1.0 / D[k] : 0.0;
+    s->nx = p.nx;
+    s->ny = p.ny;
+    s->nz = p.dim == 3 ? p.nz : 1;
+    s->halo = d.halo;
+    s->nodes = nodes_of(p);
+    s->plane = plane_of(s->nodes);
+}
+
+static int sync_check(hipStream_t st) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("stream sync: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" const char *lbm_last_error(void) { return g_err.c_str(); }
+
+extern "C" int lbm_params(const lbm_dvm_t *dvm, const lbm_problem_t *prob, lbm_params_t *out) {
+    if (!dvm || !prob || !out) return fail(LBM_E_INVALID, "lbm_params: null argument");
+    const Dvm &d = *reinterpret_cast<const Dvm *>(dvm);
+    int rc = validate(d, *prob);
+    if (rc) return rc;
+    derive(d, *prob, *out);
+    return LBM_OK;
+}
+
+extern "C" int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, size_t *pop_bytes,
+                               size_t *scratch_bytes) {
+    if (!dvm || !prob) return fail(LBM_E_INVALID, "lbm_state_bytes: null argument");
+    const Dvm &d = *reinterpret_cast<const Dvm *>(dvm);
+    int rc = validate(d, *prob);
+    if (rc) return rc;
+    Layout L = layout_of(d, *prob);
+    if (pop_bytes) *pop_bytes = L.pop_bytes;
+    if (scratch_bytes) *scratch_bytes = L.scratch_bytes;
+    return LBM_OK;
+}
+
+extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
+                                 void *pop_b, void *scratch, size_t scratch_bytes, void *stream,
+                                 lbm_solver_t **out) {
+    if (!out) return fail(LBM_E_INVALID, "lbm_solver_create: null output");
+    *out = nullptr;
+    if (!dvm || !prob || !pop_a || !pop_b || !scratch)
+        return fail(LBM_E_INVALID, "lbm_solver_create: null argument");
+    const Dvm &d = *reinterpret_cast<const Dvm *>(dvm);
+    int rc = validate(d, *prob);
+    if (rc) return rc;
+    Layout L = layout_of(d, *prob);
+    if (scratch_bytes < L.scratch_bytes) return fail(LBM_E_NO_MEMORY, "lbm_solver_create: scratch too small");
+    for (void *ptr : {pop_a, pop_b, scratch})
+        if ((uintptr_t)ptr % kAlign) return fail(LBM_E_INVALID, "lbm_solver_create: buffers must be 256-byte aligned");
+    const Storage st = (Storage)prob->storage;
+    const Launch *La = find_launch(d.dim, d.V, prob->hermite_order, st);
+    if (!La) return fail(LBM_E_UNSUPPORTED, "no kernel compiled for this velocity count / Hermite order / storage");
+    auto *s = new Solver();
+    s->dvm = d;
+    s->prob = *prob;
+    derive(d, *prob, s->par);
+    s->st = st;
+    s->L = La;
+    s->pop[0] = pop_a;
+    s->pop[1] = pop_b;
+    auto *base = (unsigned char *)scratch;
+    s->apart[0] = (double *)(base + L.off_a0);
+    s->apart[1] = (double *)(base + L.off_a1);
+    s->partial = (double *)(base + L.off_partial);
+    s->out = (double *)(base + L.off_out);
+    s->stream = (hipStream_t)stream;
+    s->nodes = nodes_of(*prob);
+    if (st == Storage::F64)
+        fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
+    else
+        fill_tables<float>(d, *prob, s->par, s->tab, s->sc);
+    // zero the wall partials so a run before init is well defined
+    hipError_t e = hipMemsetAsync(scratch, 0, L.off_partial, s->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(LBM_E_DEVICE, std::string("memset: ") + hipGetErrorString(e));
+    }
+    *out = reinterpret_cast<lbm_solver_t *>(s);
+    return LBM_OK;
+}
+
+extern "C" int lbm_solver_destroy(lbm_solver_t *h) {
+    delete reinterpret_cast<Solver *>(h);
+    return LBM_OK;
+}
+
+extern "C" int lbm_init_equilibrium(lbm_solver_t *h, const double *rho_dev, const double *u_dev) {
+    if (!h) return fail(LBM_E_INVALID, "lbm_init_equilibrium: null handle");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    s.cur = 0;
+    s.steps = 0;
+    return s.L->init(s.pop[0], s.apart[0], rho_dev, u_dev, s.tab, s.sc, s.stream, 0xFFFFFFFFu);
+}
+
+extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
+    if (!h || nsteps < 0) return fail(LBM_E_INVALID, "lbm_run: bad arguments");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        StepBuffers b{s.pop[s.cur], s.pop[1 - s.cur], s.apart[s.cur], s.apart[1 - s.cur]};
+        int rc = s.L->step(b, s.tab, s.sc, s.stream, s.xcd_remap, (uint32_t)s.steps);
+        if (rc) return rc;
+        s.cur ^= 1;
+        ++s.steps;
+    }
+    return LBM_OK;
+}
+
+static int observe_impl(Solver &s, double *rho_dev, double *u_dev, double *mdot, double *mass) {
+    int rc = s.L->observe(s.pop[s.cur], s.apart[s.cur], rho_dev, u_dev, s.partial, s.tab, s.sc, s.stream);
+    if (rc) return rc;
+    if (!mdot && !mass) return LBM_OK;
+    rc = launch_finalize(s.partial, observe_blocks(s.nodes), s.out, s.stream);
+    if (rc) return rc;
+    double host[2];
+    hipError_t e = hipMemcpyAsync(host, s.out, sizeof(host), hipMemcpyDeviceToHost, s.stream);
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("copy: ") + hipGetErrorString(e));
+    rc = sync_check(s.stream);
+    if (rc) return rc;
+    if (mdot) *mdot = s.par.mdot_scale * host[0] / (double)s.nodes;
+    if (mass) *mass = host[1];
+    return LBM_OK;
+}
+
+extern "C" int lbm_observe(lbm_solver_t *h, double *rho_dev, double *u_dev, double *mdot_host,
+                           double *mass_host) {
+    if (!h) return fail(LBM_E_INVALID, "lbm_observe: null handle");
+    return observe_impl(*reinterpret_cast<Solver *>(h), rho_dev, u_dev, mdot_host, mass_host);
+}
+
+extern "C" int lbm_run_to_tol(lbm_solver_t *h, double tol, int check_every, int64_t max_steps,
+                              int64_t *steps, double *mdot) {
+    if (!h || !(tol > 0) || check_every < 1 || max_steps < 0)
+        return fail(LBM_E_INVALID, "lbm_run_to_tol: bad arguments");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    double prev = 0.0, cur = 0.0;
+    bool have_prev = false;
+    int64_t done = 0;
+    int rc = LBM_E_NOT_CONVERGED;
+    while (done < max_steps) {
+        const int64_t n = std::min<int64_t>(check_every, max_steps - done);
+        int r = lbm_run(h, n);
+        if (r) return r;
+        done += n;
+        r = observe_impl(s, nullptr, nullptr, &cur, nullptr);
+        if (r) return r;
+        if (!std::isfinite(cur)) return fail(LBM_E_DEVICE, "mass flow is not finite");
+        if (have_prev && std::fabs(cur - prev) < tol * std::fabs(cur)) {
+            rc = LBM_OK;
+            break;
+        }
+        prev = cur;
+        have_prev = true;
+    }
+    if (steps) *steps = done;
+    if (mdot) *mdot = cur;
+    if (rc) return fail(rc, "lbm_run_to_tol: step limit reached");
+    return LBM_OK;
+}
+
+extern "C" int lbm_export_populations(lbm_solver_t *h, double *out_dev) {
+    if (!h || !out_dev) return fail(LBM_E_INVALID, "lbm_export_populations: null argument");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    return s.L->exportp(s.pop[s.cur], out_dev, s.tab, s.sc, s.stream);
+}
+
+extern "C" int lbm_import_populations(lbm_solver_t *h, const double *in_dev) {
+    if (!h || !in_dev) return fail(LBM_E_INVALID, "lbm_import_populations: null argument");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    s.cur = 0;  // the step counter is kept: a resumed run continues its numbering
+    return s.L->importp(s.pop[0], s.apart[0], in_dev, s.tab, s.sc, s.stream, 0xFFFFFFFEu);
+}
+
+extern "C" int lbm_solver_steps(const lbm_solver_t *h, int64_t *steps) {
+    if (!h || !steps) return fail(LBM_E_INVALID, "lbm_solver_steps: null argument");
+    *steps = reinterpret_cast<const Solver *>(h)->steps;
+    return LBM_OK;
+}

@@ -1,0 +1,97 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lbmdvm.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// velocity sets
+// ---------------------------------------------------------------------------
+struct Dvm {
+    int dim = 2, Q = 0, V = 0, n_groups = 0;
+    int n_rest = 0;                 // velocities with e = 0 (0 or 1), stored first
+    int halo = 0;                   // max |e_i|
+    double c = 0.0;
+    std::vector<int32_t> vel;       // V * 3 (z = 0 in 2D); rest first, then pairs (e, -e)
+    std::vector<double> w;          // V
+};
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// ---------------------------------------------------------------------------
+// kernel-side tables, passed by value as kernel arguments
+// ---------------------------------------------------------------------------
+constexpr int kMaxPairs = 20;       // up to V = 41
+
+// Per-velocity constants for a solve; velocity alpha = n_rest + 2 p (+e_p) or
+// n_rest + 2 p + 1 (-e_p).
+template <typename R>
+struct PairTable {
+    R xi[kMaxPairs][3];             // c * e_p
+    R qq[kMaxPairs][6];             // xi_x^2, xi_y^2, xi_z^2, xi_x xi_y, xi_x xi_z, xi_y xi_z
+    R w[kMaxPairs];                 // pair weight
+    R wr0[kMaxPairs];               // w * rho0
+    R inv_wr0[kMaxPairs];           // 1 / (w rho0) (deviation storage)
+    double wrd[kMaxPairs];          // w * rho0 in double
+    double shape_p[kMaxPairs];      // w (1 - dt/2 g.xi) for +e_p  (wall slots)
+    double shape_m[kMaxPairs];      // w (1 + dt/2 g.xi) for -e_p
+    int32_t ex[kMaxPairs], ey[kMaxPairs], ez[kMaxPairs];
+    int32_t exm[kMaxPairs];         // ( e_x mod nx) in [0, nx)
+    int32_t exmn[kMaxPairs];        // (-e_x mod nx) in [0, nx)
+    R w0, wr00, inv_wr00;           // rest velocity (if any)
+    double wrd0, shape0;
+};
+
+// Scalars of the collision and geometry.
+template <typename R>
+struct StepScalars {
+    R rho0, tau, omega, h, inv1h;   // h = dt / (2 tau), inv1h = 1 / (1 + h)
+    R g[3], half_dt_g[3];           // g and dt/2 g
+    R cn[6];                        // 1/n! for the Hermite terms, 0 beyond N
+    double rho0d;
+    double invD[4];                 // 1 / D(e) per face (uniform along a face)
+    int nx, ny, nz, halo;
+    int64_t plane;                  // alpha-plane stride in elements
+    int64_t nodes;
+};
+
+enum class Storage : int { F64 = LBM_F64, F32 = LBM_F32, F16DEV = LBM_F16DEV, F32RAW = LBM_F32RAW };
+
+// Buffers of one solve (device pointers).
+struct StepBuffers {
+    const void *src;
+    void *dst;
+    const double *a_cur;            // wall-flux partials of src  [face][halo][elements]
+    double *a_next;                 // wall-flux partials of dst
+};
+
+// Launchers (instantiated in the .hip translation unit).
+struct Launch {
+    int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, int xcd_remap,
+                uint32_t step);
+    int (*init)(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
+                const void *sc, hipStream_t, uint32_t step);
+    int (*observe)(const void *src, const double *a_cur, double *rho, double *u, double *partial,
+                   const void *tab, const void *sc, hipStream_t);
+    int (*exportp)(const void *src, double *out, const void *tab, const void *sc, hipStream_t);
+    int (*importp)(void *dst, double *a_out, const double *in, const void *tab, const void *sc,
+                   hipStream_t, uint32_t step);
+};
+
+// Returns nullptr when no kernel is compiled for this combination.
+const Launch *find_launch(int dim, int V, int N, Storage s);
+
+// Sum of `n` doubles laid out as partials[n][2] into out[2] in a fixed order.
+int launch_finalize(const double *partials, int n, double *out, hipStream_t st);
+
+int observe_blocks(int64_t nodes);
+
+}  // namespace lbm

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host logic (DVM solver, parameters, validation)
+matches what the paper fixes."""
+import ctypes
+import math
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_1510_08886_amd import lbm
+from tests.golden.tables import load_dvm_tables
+
+ROOT = Path(__file__).resolve().parent.parent
+
+
+def test_library_exports_every_declared_symbol():
+    header = (ROOT / "include" / "lbmdvm.h").read_text()
+    names = set(re.findall(r"^\s*(?:int|const char \*)\s*(lbm_\w+)\s*\(", header, re.M))
+    assert len(names) >= 16
+    so = lbm.lib()
+    missing = [n for n in sorted(names) if not hasattr(so, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("m", [t for t in load_dvm_tables() if t["kind"] == "minimal"],
+                         ids=lambda t: t["label"])
+def test_library_solver_reproduces_printed_tables(m):
+    c, w, V = lbm.Dvm.solve_weights(m["D"], m["gens"], m["Q"], m["c"] * 0.97, m["c"] * 1.03)
+    assert V == m["V"]
+    assert abs(c - m["c"]) <= 2e-15 * m["c"]
+    for got, want in zip(w, m["weights"]):
+        assert abs(got - want) <= 4e-15 * want
+
+
+def test_library_solver_picks_positive_root_and_matches_oracle():
+    from oracle import dvm as odvm
+    for name, spec in lbm.NAMED_DVMS.items():
+        c, w, V = lbm.Dvm.solve_weights(spec["dim"], spec["gens"], spec["Q"])
+        o = odvm.named_dvm(name)
+        assert abs(c - o.c) <= 2e-15 * o.c
+        np.testing.assert_allclose(w, o.group_weights, rtol=4e-15)
+
+
+def test_dvm_create_rejects_non_quadrature():
+    spec = lbm.NAMED_DVMS["D2V17"]
+    c, w, _ = lbm.Dvm.solve_weights(spec["dim"], spec["gens"], spec["Q"])
+    w2 = w.copy()
+    w2[1] *= 1.0 + 1e-6
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Dvm(2, spec["gens"], w2, c, 7)
+    assert e.value.code == -4
+    # exact to degree 7 is not exact to degree 9
+    with pytest.raises(lbm.LbmError):
+        lbm.Dvm(2, spec["gens"], w, c, 9)
+
+
+def test_dvm_order_rest_then_pairs():
+    d = lbm.Dvm.named("D2V37")
+    v = d.velocities
+    assert d.V == 37 and tuple(v[0]) == (0, 0)
+    for p in range(18):
+        assert tuple(v[1 + 2 * p]) == tuple(-v[2 + 2 * p])
+    assert abs(d.weights.sum() - 1) < 1e-15
+
+
+def test_params_match_paper_relations():
+    from oracle import stepper
+    from oracle import dvm as odvm
+    for name, ny, kn in (("D2V17", 40, 0.1), ("D2V37", 512, 0.05), ("D3V39", 256, 0.1)):
+        d = lbm.Dvm.named(name)
+        spec = lbm.NAMED_DVMS[name]
+        p = lbm.params(d, lbm.Problem(dim=spec["dim"], nx=1, ny=ny, nz=ny, kn=kn,
+                                      hermite_order=spec["N"]))
+        o = stepper.Params(odvm.named_dvm(name).c, ny, kn, 1e-3)
+        assert abs(p.tau - o.tau) < 1e-16 and abs(p.tau - kn * math.sqrt(2 / math.pi)) < 1e-16
+        assert abs(p.dt - o.dt) < 1e-17
+        assert abs(p.omega - o.omega) < 1e-15
+        assert abs(p.omega * (p.tau + p.dt / 2) - p.dt) < 1e-17
+        assert abs(p.g[0] - o.g[0]) < 1e-18
+        assert abs(p.u_c - 1e-3) < 1e-15
+        assert abs(p.mdot_scale - 1 / (4e-3 * kn)) < 1e-9
+        assert p.halo == 3
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("ny", 2, -1), ("hermite_order", 1, -1), ("hermite_order", 5, -1), ("kn", 0.0, -1),
+    ("g", (1e-3, 1e-4), -1), ("accommodation", 0.5, -2), ("rho0", 0.0, -1), ("nx", 0, -1),
+])
+def test_validation_errors(field, value, code):
+    d = lbm.Dvm.named("D2V17")
+    prob = lbm.Problem(dim=2, nx=4, ny=10, kn=0.1, hermite_order=3)
+    setattr(prob, field, value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.state_bytes(d, prob)
+    assert e.value.code == code
+
+
+def test_state_bytes_layout():
+    d = lbm.Dvm.named("D2V37")
+    pop, scr = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
+                                              storage="f32"))
+    assert pop == 37 * 2048 * 512 * 4
+    assert scr < 1 << 20
+    pop16, _ = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
+                                              storage="f16dev"))
+    assert pop16 == pop // 2
