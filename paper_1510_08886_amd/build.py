@@ -14,7 +14,8 @@ CSRC = PKG / "csrc"
 LIB = PKG / "liblbmdvm.so"
 BUILD_DIR = ROOT / "_build"
 
-SOURCES = ["lbm_kernels.hip", "lbm_batch.hip", "lbm_api.cpp", "lbm_dvm.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_kernels3d.hip", "lbm_batch.hip", "lbm_registry.hip", "lbm_api.cpp",
+           "lbm_dvm.cpp"]
 
 # gfx950 only; packed FP32 instructions are switched off for all device code.
 HIPCC_FLAGS = [

@@ -66,6 +66,23 @@ Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
     return L;
 }
 
+}  // namespace
+
+int match_set(const Dvm &d) {
+    for (const auto &vs : velocity_sets()) {
+        if (vs.dim != d.dim || vs.V != d.V || vs.nr != d.n_rest) continue;
+        bool same = true;
+        for (size_t q = 0; q < vs.ex.size() && same; ++q) {
+            const int *e = &d.vel[3 * (d.n_rest + 2 * q)];
+            same = e[0] == vs.ex[q] && e[1] == vs.ey[q] && e[2] == vs.ez[q];
+        }
+        if (same) return vs.id;
+    }
+    return -1;
+}
+
+namespace {
+
 int validate(const Dvm &d, const lbm_problem_t &p) {
     if (p.dim != d.dim) return fail(LBM_E_INVALID, "problem dim differs from the DVM's");
     if (p.nx < 1 || p.ny < 1 || (p.dim == 3 && p.nz < 1)) return fail(LBM_E_INVALID, "sizes must be positive");
@@ -78,6 +95,8 @@ int validate(const Dvm &d, const lbm_problem_t &p) {
         return fail(LBM_E_INVALID, "ny (and nz) must be at least the largest wall-normal |e|");
     if (p.hermite_order < 2 || p.hermite_order > (d.Q + 1) / 2)
         return fail(LBM_E_INVALID, "hermite order must satisfy 2 <= N <= (Q+1)/2");
+    if (p.hermite_order > 4)
+        return fail(LBM_E_UNSUPPORTED, "kernels implement Hermite orders up to 4");
     if (!(p.kn > 0)) return fail(LBM_E_INVALID, "kn must be positive");
     if (p.g_set && (p.g[1] != 0.0 || (p.dim == 3 && p.g[2] != 0.0)))
         return fail(LBM_E_INVALID, "the body force must be parallel to the walls (g.n = 0)");
@@ -124,7 +143,8 @@ struct Solver {
     alignas(16) unsigned char sc[sizeof(StepScalars<double>)];
     int64_t nodes = 0;
     int64_t steps = 0;
-    int xcd_remap = 1;
+    LaunchCfg cfg;                  // step-kernel launch configuration
+    int cus = 0;                    // compute units of the device
 };
 
 template <typename R>
@@ -202,12 +222,28 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
         }
     }
     for (int k = 0; k < 4; ++k) s->invD[k] = D[k] > 0 ? 1.0 / D[k] : 0.0;
+    s->hgc = 0.5 * par.dt * par.g[0] * d.c;
+    // w rho0 of the populations that leave through each face from wall row r
+    const bool dev_storage = p.storage == LBM_F32 || p.storage == LBM_F16DEV;
+    for (int r = 0; r < 8; ++r) {
+        double k[4] = {0, 0, 0, 0};
+        for (int v = 0; v < d.V; ++v) {
+            const int ey = d.vel[3 * v + 1], ez = d.vel[3 * v + 2];
+            if (ey < -r) k[0] += d.w[v] * rho0;
+            if (ey > r) k[1] += d.w[v] * rho0;
+            if (ez < -r) k[2] += d.w[v] * rho0;
+            if (ez > r) k[3] += d.w[v] * rho0;
+        }
+        for (int f = 0; f < 4; ++f) s->kA[f][r] = dev_storage ? k[f] : 0.0;
+    }
+    t->c = (R)d.c;
     s->nx = p.nx;
     s->ny = p.ny;
     s->nz = p.dim == 3 ? p.nz : 1;
     s->halo = d.halo;
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
+    s->aligned_rows = (p.nx % 64) == 0;
 }
 
 static int sync_check(hipStream_t st) {
@@ -258,8 +294,10 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
     for (void *ptr : {pop_a, pop_b, scratch})
         if ((uintptr_t)ptr % kAlign) return fail(LBM_E_INVALID, "lbm_solver_create: buffers must be 256-byte aligned");
     const Storage st = (Storage)prob->storage;
-    const Launch *La = find_launch(d.dim, d.V, prob->hermite_order, st);
-    if (!La) return fail(LBM_E_UNSUPPORTED, "no kernel compiled for this velocity count / Hermite order / storage");
+    const int set_id = match_set(d);
+    if (set_id < 0) return fail(LBM_E_UNSUPPORTED, "no kernel compiled for this velocity set");
+    const Launch *La = find_launch(set_id, st);
+    if (!La) return fail(LBM_E_UNSUPPORTED, "no kernel compiled for this velocity set / storage");
     auto *s = new Solver();
     s->dvm = d;
     s->prob = *prob;
@@ -285,6 +323,10 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
         delete s;
         return fail(LBM_E_DEVICE, std::string("memset: ") + hipGetErrorString(e));
     }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        s->cus = cus;
     *out = reinterpret_cast<lbm_solver_t *>(s);
     return LBM_OK;
 }
@@ -307,7 +349,7 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
     Solver &s = *reinterpret_cast<Solver *>(h);
     for (int64_t k = 0; k < nsteps; ++k) {
         StepBuffers b{s.pop[s.cur], s.pop[1 - s.cur], s.apart[s.cur], s.apart[1 - s.cur]};
-        int rc = s.L->step(b, s.tab, s.sc, s.stream, s.xcd_remap, (uint32_t)s.steps);
+        int rc = s.L->step(b, s.tab, s.sc, s.stream, s.cfg, (uint32_t)s.steps);
         if (rc) return rc;
         s.cur ^= 1;
         ++s.steps;
@@ -378,6 +420,15 @@ extern "C" int lbm_import_populations(lbm_solver_t *h, const double *in_dev) {
     Solver &s = *reinterpret_cast<Solver *>(h);
     s.cur = 0;  // the step counter is kept: a resumed run continues its numbering
     return s.L->importp(s.pop[0], s.apart[0], in_dev, s.tab, s.sc, s.stream, 0xFFFFFFFEu);
+}
+
+extern "C" int lbm_solver_set_launch(lbm_solver_t *h, int variant, int blocks_per_cu) {
+    if (!h || variant < 0 || variant > 1 || blocks_per_cu < 0)
+        return fail(LBM_E_INVALID, "lbm_solver_set_launch: bad arguments");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    s.cfg.variant = variant;
+    s.cfg.grid = blocks_per_cu > 0 ? blocks_per_cu * std::max(1, s.cus) : 0;
+    return LBM_OK;
 }
 
 extern "C" int lbm_solver_steps(const lbm_solver_t *h, int64_t *steps) {

@@ -1,0 +1,322 @@
+// Device-side helpers shared by the 2D channel, 3D duct and batched kernels:
+// storage encodings, stochastic rounding, compile-time pair loops, the Hermite
+// equilibrium for initial states, FP64 block sums and the export kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+
+#include "lbm_internal.h"
+#include "lbm_sets.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// storage traits: T is the stored type, R the arithmetic type.
+//   F64    : fbar in double
+//   F32    : d = fbar - w rho0 in float
+//   F32RAW : fbar in float
+//   F16DEV : d / (w rho0) in half, stochastic rounding in time steps
+// ---------------------------------------------------------------------------
+template <Storage S>
+struct St;
+template <>
+struct St<Storage::F64> {
+    using T = double;
+    using R = double;
+};
+template <>
+struct St<Storage::F32> {
+    using T = float;
+    using R = float;
+};
+template <>
+struct St<Storage::F32RAW> {
+    using T = float;
+    using R = float;
+};
+template <>
+struct St<Storage::F16DEV> {
+    using T = _Float16;
+    using R = float;
+};
+
+// PCG-family integer hash (Jarzynski & Olano, "Hash Functions for GPU
+// Rendering", JCGT 2020): one 32-bit output per 32-bit input.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+// Stochastic rounding of a float to half on the magnitude: add 13 random bits
+// below the half mantissa and truncate them. Exact in the half normal range;
+// below it (|x| < 2^-14) the final conversion rounds to nearest.
+__device__ __forceinline__ _Float16 sr_half(float x, uint32_t rnd13) {
+    uint32_t b = __float_as_uint(x);
+    b = (b + (rnd13 & 0x1FFFu)) & ~0x1FFFu;
+    return (_Float16)__uint_as_float(b);
+}
+
+template <Storage S>
+__device__ __forceinline__ typename St<S>::R decode_dev(typename St<S>::T v,
+                                                         typename St<S>::R wr0) {
+    using R = typename St<S>::R;
+    if constexpr (S == Storage::F16DEV)
+        return wr0 * (R)v;
+    else if constexpr (S == Storage::F32)
+        return v;
+    else
+        return (R)v - wr0;
+}
+
+// SRND selects stochastic rounding for half storage (time steps); init and
+// import round to nearest so that an exported state re-imports bit-exactly.
+template <Storage S, bool SRND>
+__device__ __forceinline__ typename St<S>::T encode_dev(typename St<S>::R d,
+                                                         typename St<S>::R wr0,
+                                                         typename St<S>::R inv_wr0,
+                                                         uint32_t rnd) {
+    using T = typename St<S>::T;
+    if constexpr (S == Storage::F16DEV && SRND)
+        return sr_half(d * inv_wr0, rnd);
+    else if constexpr (S == Storage::F16DEV)
+        return (T)(d * inv_wr0);
+    else if constexpr (S == Storage::F32)
+        return (T)d;
+    else
+        return (T)(d + wr0);
+}
+
+// exact FP64 value of a stored population
+template <Storage S>
+__device__ __forceinline__ double stored_value(typename St<S>::T v, double wrd) {
+    if constexpr (S == Storage::F16DEV)
+        return wrd * (1.0 + (double)(float)v);
+    else if constexpr (S == Storage::F32)
+        return wrd + (double)v;
+    else
+        return (double)v;
+}
+
+// the part of a stored population's FP64 value that varies: the whole value
+// for fbar storages, the deviation for deviation storages (whose constant
+// w rho0 parts are summed on the host)
+template <Storage S>
+__device__ __forceinline__ double stored_part(typename St<S>::T v, typename St<S>::R wr0) {
+    if constexpr (S == Storage::F16DEV)
+        return (double)wr0 * (double)(float)v;
+    else
+        return (double)v;
+}
+
+// per-node random word for stochastic rounding (n = solve-local node index)
+__device__ __forceinline__ uint32_t node_key(uint32_t n, uint32_t step) {
+    return pcg_hash(n ^ pcg_hash(step));
+}
+
+__device__ __forceinline__ uint32_t remap_block(uint32_t b, uint32_t nb) {
+    // consecutive blocks are dispatched round-robin over the 8 XCDs; give each
+    // XCD a contiguous range of tiles so its L2 sees neighbouring rows
+    const uint32_t q = nb / 8, r = nb % 8;
+    const uint32_t x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Population storage layout ("AoSoA-64"): nodes are grouped in blocks of 64
+// consecutive node indices; a block holds all V populations of its nodes, each
+// population as one contiguous 64-entry run. Element (alpha, n) lives at
+// (n / 64) * 64 V + 64 alpha + n % 64. A wavefront of 64 consecutive nodes thus
+// reads and writes whole 256-byte (FP32) runs, and the populations of one
+// block share DRAM pages, which streams far better than one plane per velocity.
+template <int V>
+__device__ __forceinline__ uint32_t aos_base(uint32_t n) {
+    return (n >> 6) * (uint32_t)(64 * V) + (n & 63u);
+}
+
+// (x mod n) for x in [-h, n + h)
+__device__ __forceinline__ int wrap_col(int x, int n, int h) {
+    if (n >= h) {
+        x = x < 0 ? x + n : x;
+        return x >= n ? x - n : x;
+    }
+    return ((x % n) + n) % n;
+}
+
+// ---------------------------------------------------------------------------
+// compile-time helpers
+// ---------------------------------------------------------------------------
+template <class F, int... P>
+__device__ __forceinline__ void for_pairs_impl(F &&f, std::integer_sequence<int, P...>) {
+    (f(std::integral_constant<int, P>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void for_pairs(F &&f) {
+    for_pairs_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// acc + E * a for a small compile-time integer E
+template <int E, typename R>
+__device__ __forceinline__ R addk(R acc, R a) {
+    if constexpr (E == 0)
+        return acc;
+    else if constexpr (E == 1)
+        return acc + a;
+    else if constexpr (E == -1)
+        return acc - a;
+    else
+        return fma(R(E), a, acc);
+}
+// E * a
+template <int E, typename R>
+__device__ __forceinline__ R mulk(R a) {
+    if constexpr (E == 1)
+        return a;
+    else if constexpr (E == -1)
+        return -a;
+    else
+        return R(E) * a;
+}
+// A x + B y for compile-time integers (0 when both vanish)
+template <int A, int B, typename R>
+__device__ __forceinline__ R lin2(R x, R y) {
+    if constexpr (A == 0 && B == 0)
+        return R(0);
+    else if constexpr (A == 0)
+        return mulk<B>(y);
+    else
+        return addk<B>(mulk<A>(x), y);
+}
+template <int A, int B, int C, typename R>
+__device__ __forceinline__ R lin3(R x, R y, R z) {
+    if constexpr (A == 0)
+        return lin2<B, C>(y, z);
+    else
+        return addk<C>(addk<B>(mulk<A>(x), y), z);
+}
+
+// encode all velocities of one node (stochastic rounding keyed by node, step)
+template <class SET, Storage S, bool SRND>
+__device__ __forceinline__ void encode_all(const typename St<S>::R (&d)[SET::V],
+                                           const PairTable<typename St<S>::R> &t, uint32_t n,
+                                           uint32_t step, typename St<S>::T (&v)[SET::V]) {
+    constexpr int NR = SET::NR;
+    uint32_t key = 0;
+    if constexpr (S == Storage::F16DEV && SRND) key = node_key(n, step);
+    if constexpr (NR) v[0] = encode_dev<S, SRND>(d[0], t.wr00, t.inv_wr00, key >> 19);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        uint32_t r = 0;
+        if constexpr (S == Storage::F16DEV && SRND) r = pcg_hash(key + (uint32_t)p);
+        v[NR + 2 * p] = encode_dev<S, SRND>(d[NR + 2 * p], t.wr0[p], t.inv_wr0[p], r);
+        v[NR + 2 * p + 1] = encode_dev<S, SRND>(d[NR + 2 * p + 1], t.wr0[p], t.inv_wr0[p], r >> 16);
+    });
+}
+
+// f^(0) - w rho0 = w [ (rho - rho0) + rho sum_{n>=1} P_n / n! ] with the scalar
+// Hermite recurrence P_{n+1} = (u.xi) P_n - n |u|^2 P_{n-1} (u^n : H^(n)(xi)).
+template <class SET, typename R>
+__device__ __forceinline__ void equilibrium_dev(const PairTable<R> &t, const StepScalars<R> &s,
+                                                double rho_d, R ux, R uy, R uz,
+                                                R (&d)[SET::V]) {
+    constexpr int NR = SET::NR;
+    const R drho = (R)(rho_d - s.rho0d);
+    const R rho = (R)rho_d;
+    const R u2 = ux * ux + uy * uy + uz * uz;
+    const R c = t.c;
+    if constexpr (NR) d[0] = t.w0 * (drho + rho * (s.cn[2] * (-u2) + s.cn[4] * R(3) * u2 * u2));
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const R ue = c * (R(SET::EX[p]) * ux + R(SET::EY[p]) * uy + R(SET::EZ[p]) * uz);
+        R Pm = 1, P = ue, even = 0, odd = ue;
+        for (int k = 1; k < 4; ++k) {
+            const R Pn = ue * P - R(k) * u2 * Pm;
+            Pm = P;
+            P = Pn;
+            if ((k + 1) & 1)
+                odd += s.cn[k + 1] * P;
+            else
+                even += s.cn[k + 1] * P;
+        }
+        d[NR + 2 * p] = t.w[p] * (drho + rho * (even + odd));
+        d[NR + 2 * p + 1] = t.w[p] * (drho + rho * (even - odd));
+    });
+}
+
+// deviations of one node from canonical FP64 populations in[alpha * nodes + n]
+template <class SET, typename R>
+__device__ __forceinline__ void import_node(const double *in, const PairTable<R> &t,
+                                            uint32_t nodes, uint32_t n, R (&d)[SET::V]) {
+    constexpr int NR = SET::NR;
+    if constexpr (NR) d[0] = (R)(in[n] - t.wrd0);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        d[NR + 2 * p] = (R)(in[(uint32_t)(NR + 2 * p) * nodes + n] - t.wrd[p]);
+        d[NR + 2 * p + 1] = (R)(in[(uint32_t)(NR + 2 * p + 1) * nodes + n] - t.wrd[p]);
+    });
+}
+
+// FP64 sums of (a, b) over a block into partial[2 * blockIdx.x + {0,1}]
+__device__ __forceinline__ void block_sum2(double a, double b, double *partial) {
+    __shared__ double sa[16], sb[16];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sa[wv] = a;
+        sb[wv] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            ta += sa[w];
+            tb += sb[w];
+        }
+        partial[2 * blockIdx.x] = ta;
+        partial[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+// canonical FP64 export [alpha][node]
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_export(const void *src, double *out,
+                                                PairTable<typename St<S>::R> t,
+                                                StepScalars<typename St<S>::R> s) {
+    using T = typename St<S>::T;
+    constexpr int NR = SET::NR;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    const uint32_t nodes = (uint32_t)s.nodes;
+    const T *f = (const T *)src + aos_base<SET::V>(n);
+    if constexpr (NR) out[n] = stored_value<S>(f[0], t.wrd0);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        for (int m = 0; m < 2; ++m) {
+            const uint32_t a = NR + 2 * p + m;
+            out[a * nodes + n] = stored_value<S>(f[64 * a], t.wrd[p]);
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+static inline int hip_ok(hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+static inline unsigned blocks_for(int64_t nodes) { return (unsigned)((nodes + 255) / 256); }
+
+struct Entry {
+    int id;
+    Storage s;
+    const Launch *l;
+};
+
+}  // namespace lbm

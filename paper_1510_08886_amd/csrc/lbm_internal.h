@@ -48,6 +48,7 @@ struct PairTable {
     int32_t exmn[kMaxPairs];        // (-e_x mod nx) in [0, nx)
     R w0, wr00, inv_wr00;           // rest velocity (if any)
     double wrd0, shape0;
+    R c;                            // lattice speed
 };
 
 // Scalars of the collision and geometry.
@@ -58,8 +59,13 @@ struct StepScalars {
     R cn[6];                        // 1/n! for the Hermite terms, 0 beyond N
     double rho0d;
     double invD[4];                 // 1 / D(e) per face (uniform along a face)
+    double hgc;                     // dt/2 * g_x * c: wall shape w (1 - hgc e_x)
+    double kA[4][8];                // per face and wall row r: sum of w rho0 over the
+                                    // velocities leaving through the face from row r
+                                    // (deviation storages; 0 otherwise)
     int nx, ny, nz, halo;
-    int64_t plane;                  // alpha-plane stride in elements
+    int64_t plane;                  // nodes rounded up to whole 64-node blocks
+    int aligned_rows;               // nx is a multiple of 64: a row starts a block
     int64_t nodes;
 };
 
@@ -73,10 +79,16 @@ struct StepBuffers {
     double *a_next;                 // wall-flux partials of dst
 };
 
+// Launch configuration of the step kernel.
+struct LaunchCfg {
+    int variant = 0;   // 0: one tile per loop iteration; 1: two-stage load pipeline
+    int grid = 0;      // blocks (0: one block per 256-node tile)
+};
+
 // Launchers (instantiated in the .hip translation unit).
 struct Launch {
-    int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, int xcd_remap,
-                uint32_t step);
+    int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t,
+                const LaunchCfg &cfg, uint32_t step);
     int (*init)(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
                 const void *sc, hipStream_t, uint32_t step);
     int (*observe)(const void *src, const double *a_cur, double *rho, double *u, double *partial,
@@ -86,8 +98,19 @@ struct Launch {
                    hipStream_t, uint32_t step);
 };
 
+// Velocity sets with compiled kernels (library velocity order).
+struct VelSetInfo {
+    std::string name;
+    int id = 0, dim = 0, V = 0, nr = 0;
+    std::vector<int> ex, ey, ez;    // +e of each pair
+};
+const std::vector<VelSetInfo> &velocity_sets();
+
+// Compiled set matching a DVM's velocity list exactly, or -1.
+int match_set(const Dvm &d);
+
 // Returns nullptr when no kernel is compiled for this combination.
-const Launch *find_launch(int dim, int V, int N, Storage s);
+const Launch *find_launch(int set_id, Storage s);
 
 // Sum of `n` doubles laid out as partials[n][2] into out[2] in a fixed order.
 int launch_finalize(const double *partials, int n, double *out, hipStream_t st);
