@@ -24,7 +24,9 @@ import lbm_workloads as wl  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_step_d2v37_f32_2048x512.json"
 KERNEL_SOURCES = ["paper_1510_08886_amd/csrc/lbm_kernels.hip",
-                  "paper_1510_08886_amd/csrc/lbm_internal.h"]
+                  "paper_1510_08886_amd/csrc/lbm_device.h",
+                  "paper_1510_08886_amd/csrc/lbm_internal.h",
+                  "paper_1510_08886_amd/csrc/lbm_sets.h"]
 
 
 def kernel_hash() -> str:
@@ -80,10 +82,6 @@ def main():
     ap.add_argument("--steps", type=int, default=wl.THROUGHPUT_D2V37["steps"])
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--variant", type=int, default=int(os.environ.get("LBM_STEP_VARIANT", "0")),
-                    help="step-kernel launch variant (0 plain, 1 load pipeline)")
-    ap.add_argument("--blocks-per-cu", type=int, default=int(os.environ.get("LBM_STEP_BPC", "0")),
-                    help="persistent blocks per CU (0: one block per tile)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of the same byte count (for counter scaling)")
     args = ap.parse_args()
@@ -114,7 +112,6 @@ def main():
     prob = lbm.Problem(dim=2, nx=c["nx"], ny=c["ny"], kn=c["kn"], ma=c["ma"], hermite_order=c["N"],
                        storage=c["storage"])
     s = lbm.Solver(d, prob, device="cuda:0")
-    s.set_launch(args.variant, args.blocks_per_cu)
     rho = torch.from_numpy(wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"]))
     s.init(rho)
     s.run(args.warmup)
@@ -150,7 +147,6 @@ def main():
         "config": {"workload": "D2V37 FP32 Poiseuille channel 2048x512, Kn=0.05, N=4, "
                                "seeded rho=1+1e-3*N(0,1)",
                    "nx": c["nx"], "ny": c["ny"], "V": d.V, "storage": "f32",
-                   "launch": {"variant": args.variant, "blocks_per_cu": args.blocks_per_cu},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -166,13 +166,6 @@ int lbm_export_populations(lbm_solver_t *s, double *out_dev);
  * bit-exactly. */
 int lbm_import_populations(lbm_solver_t *s, const double *in_dev);
 
-/* Launch configuration of the step kernel (performance only; results do not
- * depend on it): variant 0 loads, collides and stores one 256-node tile per
- * loop iteration, variant 1 keeps the next tile's loads in flight while the
- * current one is collided; blocks_per_cu > 0 runs a persistent grid of that
- * many blocks per compute unit, 0 launches one block per tile (default). */
-int lbm_solver_set_launch(lbm_solver_t *s, int variant, int blocks_per_cu);
-
 /* Steps taken since the last init/import. */
 int lbm_solver_steps(const lbm_solver_t *s, int64_t *steps);
 

@@ -143,8 +143,6 @@ struct Solver {
     alignas(16) unsigned char sc[sizeof(StepScalars<double>)];
     int64_t nodes = 0;
     int64_t steps = 0;
-    LaunchCfg cfg;                  // step-kernel launch configuration
-    int cus = 0;                    // compute units of the device
 };
 
 template <typename R>
@@ -323,10 +321,6 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
         delete s;
         return fail(LBM_E_DEVICE, std::string("memset: ") + hipGetErrorString(e));
     }
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-        s->cus = cus;
     *out = reinterpret_cast<lbm_solver_t *>(s);
     return LBM_OK;
 }
@@ -349,7 +343,7 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
     Solver &s = *reinterpret_cast<Solver *>(h);
     for (int64_t k = 0; k < nsteps; ++k) {
         StepBuffers b{s.pop[s.cur], s.pop[1 - s.cur], s.apart[s.cur], s.apart[1 - s.cur]};
-        int rc = s.L->step(b, s.tab, s.sc, s.stream, s.cfg, (uint32_t)s.steps);
+        int rc = s.L->step(b, s.tab, s.sc, s.stream, (uint32_t)s.steps);
         if (rc) return rc;
         s.cur ^= 1;
         ++s.steps;
@@ -420,15 +414,6 @@ extern "C" int lbm_import_populations(lbm_solver_t *h, const double *in_dev) {
     Solver &s = *reinterpret_cast<Solver *>(h);
     s.cur = 0;  // the step counter is kept: a resumed run continues its numbering
     return s.L->importp(s.pop[0], s.apart[0], in_dev, s.tab, s.sc, s.stream, 0xFFFFFFFEu);
-}
-
-extern "C" int lbm_solver_set_launch(lbm_solver_t *h, int variant, int blocks_per_cu) {
-    if (!h || variant < 0 || variant > 1 || blocks_per_cu < 0)
-        return fail(LBM_E_INVALID, "lbm_solver_set_launch: bad arguments");
-    Solver &s = *reinterpret_cast<Solver *>(h);
-    s.cfg.variant = variant;
-    s.cfg.grid = blocks_per_cu > 0 ? blocks_per_cu * std::max(1, s.cus) : 0;
-    return LBM_OK;
 }
 
 extern "C" int lbm_solver_steps(const lbm_solver_t *h, int64_t *steps) {

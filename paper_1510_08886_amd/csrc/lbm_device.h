@@ -117,14 +117,6 @@ __device__ __forceinline__ uint32_t node_key(uint32_t n, uint32_t step) {
     return pcg_hash(n ^ pcg_hash(step));
 }
 
-__device__ __forceinline__ uint32_t remap_block(uint32_t b, uint32_t nb) {
-    // consecutive blocks are dispatched round-robin over the 8 XCDs; give each
-    // XCD a contiguous range of tiles so its L2 sees neighbouring rows
-    const uint32_t q = nb / 8, r = nb % 8;
-    const uint32_t x = b % 8, k = b / 8;
-    return x * q + (x < r ? x : r) + k;
-}
-
 // Population storage layout ("AoSoA-64"): nodes are grouped in blocks of 64
 // consecutive node indices; a block holds all V populations of its nodes, each
 // population as one contiguous 64-entry run. Element (alpha, n) lives at

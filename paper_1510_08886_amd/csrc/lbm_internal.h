@@ -79,16 +79,9 @@ struct StepBuffers {
     double *a_next;                 // wall-flux partials of dst
 };
 
-// Launch configuration of the step kernel.
-struct LaunchCfg {
-    int variant = 0;   // 0: one tile per loop iteration; 1: two-stage load pipeline
-    int grid = 0;      // blocks (0: one block per 256-node tile)
-};
-
 // Launchers (instantiated in the .hip translation unit).
 struct Launch {
-    int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t,
-                const LaunchCfg &cfg, uint32_t step);
+    int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, uint32_t step);
     int (*init)(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
                 const void *sc, hipStream_t, uint32_t step);
     int (*observe)(const void *src, const double *a_cur, double *rho, double *u, double *partial,

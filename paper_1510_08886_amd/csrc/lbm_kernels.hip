@@ -271,77 +271,27 @@ __device__ __forceinline__ void scatter2d(typename St<S>::T *__restrict__ dst,
     }
 }
 
-// One block of 256 threads per tile of 256 consecutive nodes; the grid walks
-// the tiles with stride gridDim.x (gridDim.x = number of tiles gives one tile
-// per block). With PIPE the loop handles a tile while the loads of the next
-// one are in flight (two register buffers); without it each iteration loads,
-// collides and stores one tile. Every block leaves the loop once its tile
-// index passes the last tile.
-template <class SET, Storage S, bool PIPE>
-__device__ __forceinline__ void step2d_body(const StepBuffers &b, const PairTable<typename St<S>::R> &t,
-                                            const StepScalars<typename St<S>::R> &s, uint32_t step) {
-    using R = typename St<S>::R;
-    using T = typename St<S>::T;
-    const uint32_t nodes = (uint32_t)s.nodes;
-    const uint32_t ntiles = (nodes + 255u) / 256u;
-    const uint32_t G = gridDim.x;
-    const uint32_t nx = (uint32_t)s.nx;
-    const T *src = (const T *)b.src;
-    T *dst = (T *)b.dst;
-    struct Node {
-        int i, j;
-        bool active;
-    };
-    auto load = [&](uint32_t tile, T (&raw)[SET::V]) -> Node {
-        Node c{0, 0, false};
-        if (tile < ntiles) {
-            const uint32_t n = tile * 256u + threadIdx.x;
-            if (n < nodes) {
-                c.j = (int)(n / nx);
-                c.i = (int)(n - (uint32_t)c.j * nx);
-                c.active = true;
-                issue2d<SET, S>(src, s, c.i, c.j, raw);
-            }
-        }
-        return c;
-    };
-    auto finish = [&](const T (&raw)[SET::V], Node c) {
-        if (!c.active) return;
-        R d[SET::V];
-        complete2d<SET, S>(raw, b.a_cur, t, s, c.i, c.j, d);
-        relax2d<SET, R>(d, t, s, t.c);
-        scatter2d<SET, S, true>(dst, b.a_next, t, s, c.i, c.j, d, step);
-    };
-    if constexpr (PIPE) {
-        T cur[SET::V], nxt[SET::V];
-        uint32_t tile = blockIdx.x;
-        Node c = load(tile, cur);
-        while (tile < ntiles) {
-            const Node cn = load(tile + G, nxt);   // in flight during the collision below
-            finish(cur, c);
-#pragma unroll
-            for (int a = 0; a < SET::V; ++a) cur[a] = nxt[a];
-            c = cn;
-            tile += G;
-        }
-    } else {
-        T raw[SET::V];
-        const Node c = load(blockIdx.x, raw);
-        finish(raw, c);
-        (void)G;
-    }
-}
-
+// One block of 256 threads per tile of 256 consecutive nodes. Each thread
+// issues the pull loads of all its velocities before it decodes any of them,
+// so a wavefront has its whole gather in flight at once; the wall slots are
+// patched after the loads. (Measured on MI355X: this beats a persistent grid
+// with a two-stage load pipeline, whose second register buffer halves the
+// occupancy, and 128- or 512-node tiles.)
 template <class SET, Storage S>
 __global__ __launch_bounds__(256) void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t,
                                                 StepScalars<typename St<S>::R> s, uint32_t step) {
-    step2d_body<SET, S, false>(b, t, s, step);
-}
-
-template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_step2d_pipe(StepBuffers b, PairTable<typename St<S>::R> t,
-                                                     StepScalars<typename St<S>::R> s, uint32_t step) {
-    step2d_body<SET, S, true>(b, t, s, step);
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    const int j = (int)(n / (uint32_t)s.nx);
+    const int i = (int)(n - (uint32_t)j * s.nx);
+    T raw[SET::V];
+    issue2d<SET, S>((const T *)b.src, s, i, j, raw);
+    R d[SET::V];
+    complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
+    relax2d<SET, R>(d, t, s, t.c);
+    scatter2d<SET, S, true>((T *)b.dst, b.a_next, t, s, i, j, d, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,15 +371,11 @@ template <class SET, Storage S>
 struct L2 {
     using R = typename St<S>::R;
     static int step(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
-                    const LaunchCfg &cfg, uint32_t stp) {
+                    uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        const unsigned tiles = blocks_for(s.nodes);
-        const unsigned g = cfg.grid > 0 && (unsigned)cfg.grid < tiles ? (unsigned)cfg.grid : tiles;
-        if (cfg.variant == 1)
-            hipLaunchKernelGGL((k_step2d_pipe<SET, S>), dim3(g), dim3(256), 0, st, b, t, s, stp);
-        else
-            hipLaunchKernelGGL((k_step2d<SET, S>), dim3(g), dim3(256), 0, st, b, t, s, stp);
+        hipLaunchKernelGGL((k_step2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, b, t,
+                           s, stp);
         return hip_ok(hipGetLastError(), "step kernel launch");
     }
     static int init(void *dst, double *a_out, const double *rho, const double *u, const void *tab,

@@ -80,7 +80,6 @@ SIGNATURES = {
     "lbm_export_populations": ([_P, _P], _I),
     "lbm_import_populations": ([_P, _P], _I),
     "lbm_solver_steps": ([_P, ctypes.POINTER(_I64)], _I),
-    "lbm_solver_set_launch": ([_P, _I, _I], _I),
 }
 
 
@@ -295,11 +294,6 @@ class Solver:
         p = pops.to(self.device, torch.float64).contiguous().reshape(-1)
         self._keep = (p,)
         check(lib().lbm_import_populations(self._h, _ptr(p)), "lbm_import_populations")
-        return self
-
-    def set_launch(self, variant: int = 0, blocks_per_cu: int = 0):
-        check(lib().lbm_solver_set_launch(self._h, int(variant), int(blocks_per_cu)),
-              "lbm_solver_set_launch")
         return self
 
     @property
