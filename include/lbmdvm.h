@@ -169,6 +169,83 @@ int lbm_import_populations(lbm_solver_t *s, const double *in_dev);
 /* Steps taken since the last init/import. */
 int lbm_solver_steps(const lbm_solver_t *s, int64_t *steps);
 
+/* ---- batched and served channel solves -------------------------------------
+ * Many independent channels (2D, nx = 1: the streamwise-invariant plane
+ * Poiseuille problem of Section VI) run together, each to a steady-state
+ * tolerance on the mass flow. One workgroup owns one channel at a time and keeps
+ * its populations in LDS while it steps; between launches a channel's state
+ * lives in HBM, in the caller's pool. Every channel performs exactly the
+ * per-node arithmetic of lbm_run, and its convergence test is that of
+ * lbm_run_to_tol, so a result does not depend on which other channels share a
+ * launch (tested bit for bit).
+ *
+ * Pool: a caller-owned device buffer. The batch keeps its slot table, velocity
+ * tables and work counter at the start of the pool and carves per-channel state
+ * (V * ny stored populations) from the rest; a request is admitted when a slot
+ * and enough pool bytes are free ("admission by memory"). */
+
+typedef struct {
+    uint64_t req_id;   /* the caller's identifier */
+    int status;        /* LBM_OK converged, LBM_E_NOT_CONVERGED step cap reached,
+                          LBM_E_DEVICE mass flow not finite */
+    int ny;
+    int64_t steps;     /* steps taken */
+    double mdot;       /* last mass flow evaluated (Eq. pf.1) */
+    double kn;
+} lbm_result_t;
+
+typedef struct {
+    int active;        /* channels resident on the device */
+    int queued;        /* submitted, not yet admitted */
+    int done;          /* finished, not yet returned by poll */
+    int threads;       /* workgroup size in use */
+    int quantum;       /* steps per launch in the served mode */
+    int64_t launches;  /* kernel launches so far */
+    size_t pool_used;  /* state bytes allocated */
+    size_t pool_free;
+} lbm_batch_stats_t;
+
+/* Create a batch with up to max_slots resident channels, all with the given
+ * storage (LBM_F32, LBM_F16DEV or LBM_F32RAW), over the caller's device pool
+ * (256-byte aligned) and HIP stream. LBM_E_NO_MEMORY if the pool cannot hold
+ * the slot table. */
+int lbm_batch_create(int max_slots, int storage, void *pool, size_t pool_bytes, void *stream,
+                     lbm_batch_t **out);
+int lbm_batch_destroy(lbm_batch_t *b);
+
+/* Queue one channel solve: prob->dim = 2, prob->nx = 1, prob->storage equal
+ * to the batch's; the DVM must have a compiled kernel. It runs from the rest
+ * state rho0 w until |mdot_k - mdot_{k-1}| < tol |mdot_k| with mdot evaluated
+ * every check_every steps, or until max_steps. LBM_E_NO_MEMORY if it can
+ * never fit the pool or the LDS of one workgroup. */
+int lbm_batch_submit(lbm_batch_t *b, const lbm_dvm_t *dvm, const lbm_problem_t *prob, double tol,
+                     int check_every, int64_t max_steps, uint64_t req_id);
+
+/* Served mode, non-blocking: if the launch in flight has finished, harvest
+ * finished channels and free their slots and pool bytes; admit queued requests
+ * while slots and bytes allow; launch the next quantum over the resident
+ * channels. Finished results (up to cap) go to out, their count to *n_out. */
+int lbm_batch_poll(lbm_batch_t *b, lbm_result_t *out, int cap, int *n_out);
+
+/* Blocking: poll until every submitted request has finished. */
+int lbm_batch_drain(lbm_batch_t *b, lbm_result_t *out, int cap, int *n_out);
+
+/* Batch mode, blocking: admit every queued request (they must all fit), then
+ * run them in ONE persistent launch captured in a HIP graph: workgroups take
+ * channels from a device work queue (longest estimated first) and step each to
+ * its tolerance. */
+int lbm_batch_run_persistent(lbm_batch_t *b, lbm_result_t *out, int cap, int *n_out);
+
+/* Workgroup size (64..1024, multiple of 64) and steps per served launch. */
+int lbm_batch_tune(lbm_batch_t *b, int threads, int quantum);
+
+/* Time short trial launches of the queued requests for each candidate
+ * workgroup size, keep the fastest (results are identical for every choice).
+ * The queued requests stay queued. */
+int lbm_batch_autotune(lbm_batch_t *b, int trial_steps, int *threads_out);
+
+int lbm_batch_stats(const lbm_batch_t *b, lbm_batch_stats_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -244,6 +244,19 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->aligned_rows = (p.nx % 64) == 0;
 }
 
+// Validated parameters and kernel tables of one problem (used by the batch).
+int problem_params(const Dvm &d, const lbm_problem_t &p, lbm_params_t &par, void *tab, void *sc,
+                   bool f64) {
+    int rc = validate(d, p);
+    if (rc) return rc;
+    derive(d, p, par);
+    if (f64)
+        fill_tables<double>(d, p, par, tab, sc);
+    else
+        fill_tables<float>(d, p, par, tab, sc);
+    return LBM_OK;
+}
+
 static int sync_check(hipStream_t st) {
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("stream sync: ") + hipGetErrorString(e));

@@ -51,6 +51,17 @@ class ParamsC(ctypes.Structure):
                 ("mdot_scale", ctypes.c_double), ("V", ctypes.c_int), ("halo", ctypes.c_int)]
 
 
+class ResultC(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("status", ctypes.c_int), ("ny", ctypes.c_int),
+                ("steps", ctypes.c_int64), ("mdot", ctypes.c_double), ("kn", ctypes.c_double)]
+
+
+class BatchStatsC(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int), ("queued", ctypes.c_int), ("done", ctypes.c_int),
+                ("threads", ctypes.c_int), ("quantum", ctypes.c_int), ("launches", ctypes.c_int64),
+                ("pool_used", ctypes.c_size_t), ("pool_free", ctypes.c_size_t)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -80,6 +91,15 @@ SIGNATURES = {
     "lbm_export_populations": ([_P, _P], _I),
     "lbm_import_populations": ([_P, _P], _I),
     "lbm_solver_steps": ([_P, ctypes.POINTER(_I64)], _I),
+    "lbm_batch_create": ([_I, _I, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)], _I),
+    "lbm_batch_destroy": ([_P], _I),
+    "lbm_batch_submit": ([_P, _P, ctypes.POINTER(ProblemC), _D, _I, _I64, ctypes.c_uint64], _I),
+    "lbm_batch_poll": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
+    "lbm_batch_drain": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
+    "lbm_batch_run_persistent": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
+    "lbm_batch_tune": ([_P, _I, _I], _I),
+    "lbm_batch_autotune": ([_P, _I, _IP], _I),
+    "lbm_batch_stats": ([_P, ctypes.POINTER(BatchStatsC)], _I),
 }
 
 
@@ -306,6 +326,99 @@ class Solver:
         h = getattr(self, "_h", None)
         if h:
             lib().lbm_solver_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+STATUS_NAMES = {0: "converged", -6: "not_converged", -5: "failed"}
+
+
+class Batch:
+    """Many independent channels (nx = 1) stepped together, each to a
+    steady-state tolerance; populations resident in LDS while stepping and in
+    the caller's HBM pool (a torch tensor) in between."""
+
+    def __init__(self, max_slots: int, storage: str = "f32", pool_bytes: int = 256 << 20,
+                 device: str = "cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        if self.pool.data_ptr() % 256:
+            raise RuntimeError("pool is not 256-byte aligned")
+        # graph capture needs a stream other than the legacy default stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.storage = storage
+        self.max_slots = max_slots
+        h = _P()
+        check(lib().lbm_batch_create(int(max_slots), STORAGE[storage], _ptr(self.pool), int(pool_bytes),
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "lbm_batch_create")
+        self._h = h
+        self._dvms = []
+        self._buf = (ResultC * max(64, max_slots * 4))()
+
+    def submit(self, dvm: Dvm, ny: int, kn: float, ma: float = 1e-3, N: int | None = None,
+               tol: float = 1e-8, check_every: int = 100, max_steps: int = 10**7,
+               req_id: int = 0, rho0: float = 1.0):
+        prob = Problem(dim=2, nx=1, ny=int(ny), kn=float(kn), ma=float(ma),
+                       hermite_order=N if N is not None else getattr(dvm, "default_N", 3),
+                       storage=self.storage, rho0=rho0)
+        pc = prob.to_c()
+        self._dvms.append(dvm)
+        check(lib().lbm_batch_submit(self._h, dvm._h, ctypes.byref(pc), float(tol), int(check_every),
+                                     int(max_steps), ctypes.c_uint64(int(req_id))), "lbm_batch_submit")
+
+    def _results(self, n):
+        out = []
+        for k in range(n):
+            r = self._buf[k]
+            out.append(dict(req_id=int(r.req_id), status=STATUS_NAMES.get(r.status, r.status),
+                            ny=r.ny, steps=int(r.steps), mdot=r.mdot, kn=r.kn))
+        return out
+
+    def _call(self, fn, name):
+        res = []
+        while True:
+            n = ctypes.c_int()
+            check(fn(self._h, self._buf, len(self._buf), ctypes.byref(n)), name)
+            res += self._results(n.value)
+            if n.value < len(self._buf):
+                return res
+
+    def poll(self):
+        return self._call(lib().lbm_batch_poll, "lbm_batch_poll")
+
+    def drain(self):
+        return self._call(lib().lbm_batch_drain, "lbm_batch_drain")
+
+    def run_persistent(self):
+        return self._call(lib().lbm_batch_run_persistent, "lbm_batch_run_persistent")
+
+    def tune(self, threads: int, quantum: int = 1000):
+        check(lib().lbm_batch_tune(self._h, int(threads), int(quantum)), "lbm_batch_tune")
+        return self
+
+    def autotune(self, trial_steps: int = 300) -> int:
+        t = ctypes.c_int()
+        check(lib().lbm_batch_autotune(self._h, int(trial_steps), ctypes.byref(t)), "lbm_batch_autotune")
+        return t.value
+
+    def stats(self):
+        st = BatchStatsC()
+        check(lib().lbm_batch_stats(self._h, ctypes.byref(st)), "lbm_batch_stats")
+        return {f: getattr(st, f) for f, _ in BatchStatsC._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lbm_batch_destroy(h)
             self._h = None
 
     def __del__(self):
