@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark of the fused stream + wall + collide step on one MI355X.
 
-Workload: the D2V37 FP32 throughput channel, 2048 x 512 nodes (periodic x,
+Headline: the D2V37 FP32 throughput channel, 2048 x 512 nodes (periodic x,
 diffuse Maxwell walls at y), Kn = 0.05, Hermite order 4, seeded density
 1 + 1e-3 N(0,1), u = 0. One benchmark step = one lattice update of the whole
-grid. Prints one JSON line.
+grid: MLUPS and the HBM roofline fraction. Also reported on the same line: the
+batched 64-channel Kn sweep (solves/s vs one solve at a time with plain
+kernels) and the served 1000-request trace (p50/p99 latency, solves/s). Prints
+one JSON line.
 """
 from __future__ import annotations
 
@@ -25,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_step_d2v37_f32_2048x512.json"
 KERNEL_SOURCES = ["paper_1510_08886_amd/csrc/lbm_kernels.hip",
                   "paper_1510_08886_amd/csrc/lbm_device.h",
+                  "paper_1510_08886_amd/csrc/lbm_node2d.h",
                   "paper_1510_08886_amd/csrc/lbm_internal.h",
                   "paper_1510_08886_amd/csrc/lbm_sets.h"]
 
@@ -76,12 +80,110 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"(after 1 warm-up step), {el:.1f} s"}
 
 
+def _oracle_mdot(name, ny, kn, steps):
+    from oracle import dvm as odvm
+    from oracle import stepper
+    N = 4 if name == "D2V37" else 3
+    o = stepper.OracleSolver(odvm.named_dvm(name), nx=1, ny=ny, kn=kn, ma=1e-3, N=N).init()
+    o.run(steps)
+    return o.observe()["mdot"]
+
+
+def batched_block(n_oracle: int = 6):
+    """64-channel D2V37 Kn sweep: one persistent launch (hipGraph) vs the same
+    solves one at a time with plain step kernels, FP32 and FP16 deviations,
+    mass-flow error against the FP64 oracle at equal step counts on the
+    cheapest channels."""
+    import numpy as np
+    from paper_1510_08886_amd import serve
+    cfg = wl.SWEEP
+    chans = wl.sweep_channels(cfg["channels"], seed=cfg["seed"])
+    f32 = serve.batched_sweep(chans, storage="f32", tol=cfg["tol"], check_every=cfg["check_every"])
+    steps32 = [r["steps"] for r in f32["results"]]
+    # FP16 stochastic rounding keeps a noise floor above a 1e-8 relative change:
+    # cap each channel at 1.5x the steps its FP32 solve took
+    caps = [int(np.ceil(1.5 * st / 100) * 100) for st in steps32]
+    f16 = serve.batched_sweep(chans, storage="f16dev", tol=cfg["tol"], check_every=cfg["check_every"],
+                              max_steps=caps)
+    plain = serve.plain_sweep(chans, storage="f32", tol=cfg["tol"], check_every=cfg["check_every"])
+    same = all(a["steps"] == b["steps"] and abs(a["mdot"] - b["mdot"]) <= 1e-13 * abs(b["mdot"])
+               for a, b in zip(f32["results"], plain["results"]))
+    # accuracy on the cheapest channels (oracle time ~ ny * steps)
+    order = sorted(range(len(chans)), key=lambda k: chans[k]["ny"] * steps32[k])[:n_oracle]
+    err32, err16 = [], []
+    for k in order:
+        want = _oracle_mdot(cfg["dvm"], chans[k]["ny"], chans[k]["kn"], steps32[k])
+        err32.append(abs(f32["results"][k]["mdot"] - want) / abs(want))
+        want16 = _oracle_mdot(cfg["dvm"], chans[k]["ny"], chans[k]["kn"], f16["results"][k]["steps"])
+        err16.append(abs(f16["results"][k]["mdot"] - want16) / abs(want16))
+    n = len(chans)
+    return {
+        "workload": "64 D2V37 channels, Nx=1, Ny~U[16,512], Kn log-uniform [0.01,1], Ma=1e-3, "
+                    "tol 1e-8 on mdot every 100 steps",
+        "solves_per_s": round(n / f32["makespan_s"], 2),
+        "makespan_s": round(f32["makespan_s"], 4),
+        "plain_solves_per_s": round(n / plain["total_s"], 2),
+        "plain_total_s": round(plain["total_s"], 3),
+        "speedup_vs_plain": round(plain["total_s"] / f32["makespan_s"], 2),
+        "converged": sum(r["status"] == "converged" for r in f32["results"]),
+        "total_steps": int(sum(steps32)),
+        "autotuned_threads": f32["threads"],
+        "batched_equals_plain": bool(same),
+        "fp16dev": {"makespan_s": round(f16["makespan_s"], 4),
+                    "solves_per_s": round(n / f16["makespan_s"], 2),
+                    "converged": sum(r["status"] == "converged" for r in f16["results"]),
+                    "cap": "1.5x the FP32 steps per channel",
+                    "autotuned_threads": f16["threads"]},
+        "mdot_rel_err_vs_oracle": {"channels": len(order), "f32_max": max(err32),
+                                   "f16dev_max": max(err16),
+                                   "note": "oracle at the same step count, cheapest channels"},
+    }
+
+
+def serving_block(n_plain: int):
+    """1000-request Poisson trace (200/s) served with continuous batching vs
+    the first n_plain requests run one at a time in arrival order."""
+    import numpy as np
+    from paper_1510_08886_amd import serve
+    cfg = wl.SERVE
+    trace = wl.serve_trace(cfg["requests"], seed=cfg["seed"], rate=cfg["rate"])
+    s = serve.serve(trace, tol=cfg["tol"], check_every=cfg["check_every"])
+    lat = s["latency_s"]
+    first = trace[:n_plain]
+    sp = serve.serve(first, tol=cfg["tol"], check_every=cfg["check_every"])
+    p = serve.serve_plain_fifo(first, tol=cfg["tol"], check_every=cfg["check_every"])
+    same = all(a["steps"] == b["steps"] and abs(a["mdot"] - b["mdot"]) <= 1e-13 * abs(b["mdot"])
+               for a, b in zip(sp["results"], p["results"]))
+    span = max(r["t_done"] for r in s["results"]) - trace[0]["t"]
+    return {
+        "workload": "1000 requests, Poisson 200/s, Ny~U[16,1024], Kn log-uniform [0.01,1], "
+                    "DVM in {D2V17, D2V37}, FP32, tol 1e-8",
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+        "solves_per_s": round(len(trace) / span, 2),
+        "wall_s": round(s["wall_s"], 3),
+        "launches": s["launches"],
+        "max_resident": s["max_active"],
+        "prefix": {"requests": n_plain,
+                   "served_p50_s": round(float(np.percentile(sp["latency_s"], 50)), 4),
+                   "served_p99_s": round(float(np.percentile(sp["latency_s"], 99)), 4),
+                   "plain_p50_s": round(float(np.percentile(p["latency_s"], 50)), 4),
+                   "plain_p99_s": round(float(np.percentile(p["latency_s"], 99)), 4),
+                   "plain_solves_per_s": round(n_plain / p["busy_s"], 2),
+                   "served_equals_plain": bool(same)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=wl.THROUGHPUT_D2V37["steps"])
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched Kn sweep")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--plain-serve-requests", type=int, default=100,
+                    help="prefix of the serving trace run by the one-at-a-time plain baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of the same byte count (for counter scaling)")
     args = ap.parse_args()
@@ -154,6 +256,11 @@ def main():
         "wall_s": round(wall, 3),
         "mdot_after": obs["mdot"],
     }
+    s.close()
+    if not args.no_batch:
+        out["batched"] = batched_block()
+    if not args.no_serve:
+        out["serving"] = serving_block(args.plain_serve_requests)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
