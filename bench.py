@@ -6,8 +6,8 @@ diffuse Maxwell walls at y), Kn = 0.05, Hermite order 4, seeded density
 1 + 1e-3 N(0,1), u = 0. One benchmark step = one lattice update of the whole
 grid: MLUPS and the HBM roofline fraction. Also reported on the same line: the
 batched 64-channel Kn sweep (solves/s vs one solve at a time with plain
-kernels) and the served 1000-request trace (p50/p99 latency, solves/s). Prints
-one JSON line.
+kernels), the served 1000-request trace (p50/p99 latency, solves/s) and the
+3D D3V39 duct with FP32 and FP16-deviation populations. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -174,6 +174,52 @@ def serving_block(n_plain: int):
     }
 
 
+def duct_block():
+    """3D square duct on D3V39, 128 x 256 x 256 (periodic x, diffuse Maxwell
+    walls on the four y and z faces), Kn = 0.1, from rest, 500 steps with FP32
+    and FP16-deviation populations; mass-flow error against the FP64 oracle's
+    streamwise-invariant (one x column) run of the same duct, stored under
+    tests/golden/ by a script that calls only the oracle."""
+    import torch
+
+    from paper_1510_08886_amd import lbm
+
+    c = wl.DUCT_D3V39
+    gold = {}
+    for line in (ROOT / "tests" / "golden" / "duct_d3v39_mdot.txt").read_text().splitlines():
+        if line and not line.startswith("#"):
+            t = line.split()
+            gold[int(t[0])] = float(t[1])
+    want = gold[c["steps"]]
+    d = lbm.Dvm.named(c["dvm"])
+    nodes = c["nx"] * c["ny"] * c["nz"]
+    out = {"workload": "D3V39 N=3 square duct 128x256x256, Kn=0.1, Ma=1e-3, from rest, "
+                       f"{c['steps']} steps", "oracle_mdot": want}
+    for storage, size in (("f32", 4), ("f16dev", 2)):
+        prob = lbm.Problem(dim=3, nx=c["nx"], ny=c["ny"], nz=c["nz"], kn=c["kn"], ma=c["ma"],
+                           hermite_order=c["N"], storage=storage)
+        s = lbm.Solver(d, prob, device="cuda:0").init()
+        m0 = s.observe()["mass"]
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.run(c["steps"])
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        ob = s.observe()
+        gbs = 2 * d.V * size * nodes / (ms * 1e-3 / c["steps"]) / 1e9
+        out[storage] = {"mlups": round(nodes * c["steps"] / (ms * 1e-3) / 1e6, 1),
+                        "ms_per_step": ms / c["steps"],
+                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "mdot": ob["mdot"],
+                        "mdot_rel_err_vs_oracle": abs(ob["mdot"] - want) / abs(want),
+                        "mass_drift": abs(ob["mass"] - m0) / m0}
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +228,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Kn sweep")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--no-duct", action="store_true", help="skip the 3D duct runs")
     ap.add_argument("--plain-serve-requests", type=int, default=100,
                     help="prefix of the serving trace run by the one-at-a-time plain baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -261,6 +308,8 @@ def main():
         out["batched"] = batched_block()
     if not args.no_serve:
         out["serving"] = serving_block(args.plain_serve_requests)
+    if not args.no_duct:
+        out["duct"] = duct_block()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "lbm_internal.h"
 
@@ -49,8 +50,14 @@ struct Layout {
     size_t pop_bytes = 0;
     size_t apart_bytes = 0;     // one copy of the wall partials
     size_t partial_bytes = 0;   // observation block partials
-    size_t off_a0 = 0, off_a1 = 0, off_partial = 0, off_out = 0, scratch_bytes = 0;
+    size_t invd_bytes = 0;      // 1 / D(e) per face and position along it
+    size_t off_a0 = 0, off_a1 = 0, off_invd = 0, off_partial = 0, off_out = 0, scratch_bytes = 0;
 };
+
+// positions along a face: a duct's y faces vary with z, its z faces with y
+int64_t face_positions(const lbm_problem_t &p) {
+    return p.dim == 3 ? std::max(p.ny, p.nz) : 1;
+}
 
 Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
     Layout L;
@@ -58,9 +65,11 @@ Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
     L.pop_bytes = align_up((size_t)d.V * plane_of(nodes) * storage_bytes(p.storage));
     L.apart_bytes = align_up(sizeof(double) * 4 * std::max(1, d.halo) * face_elems(p));
     L.partial_bytes = align_up(sizeof(double) * 2 * observe_blocks(nodes));
+    L.invd_bytes = align_up(sizeof(double) * 4 * face_positions(p));
     L.off_a0 = 0;
     L.off_a1 = L.apart_bytes;
-    L.off_partial = 2 * L.apart_bytes;
+    L.off_invd = 2 * L.apart_bytes;
+    L.off_partial = L.off_invd + L.invd_bytes;
     L.off_out = L.off_partial + L.partial_bytes;
     L.scratch_bytes = L.off_out + align_up(2 * sizeof(double));
     return L;
@@ -137,6 +146,8 @@ struct Solver {
     double *apart[2] = {nullptr, nullptr};
     double *partial = nullptr;
     double *out = nullptr;
+    double *invd = nullptr;
+    std::vector<double> invd_host;  // source of the asynchronous upload of invd
     int cur = 0;
     hipStream_t stream = nullptr;
     alignas(16) unsigned char tab[sizeof(PairTable<double>)];
@@ -159,10 +170,12 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
         for (int k = 0; k < 3; ++k) gx += par.g[k] * d.c * d.vel[3 * v + k];
         return d.w[v] * (1.0 - 0.5 * par.dt * gx);
     };
+    // half deviations are stored as 1024 d / (w rho0) (power of two: exact)
+    const double enc = p.storage == LBM_F16DEV ? 1024.0 : 1.0;
     if (d.n_rest) {
         t->w0 = (R)d.w[0];
-        t->wr00 = (R)(d.w[0] * rho0);
-        t->inv_wr00 = (R)(1.0 / (d.w[0] * rho0));
+        t->wr00 = (R)(d.w[0] * rho0 / enc);
+        t->inv_wr00 = (R)(enc / (d.w[0] * rho0));
         t->wrd0 = d.w[0] * rho0;
         t->shape0 = shape(0);
     }
@@ -180,8 +193,8 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
         t->qq[q][4] = (R)(xi[0] * xi[2]);
         t->qq[q][5] = (R)(xi[1] * xi[2]);
         t->w[q] = (R)d.w[v];
-        t->wr0[q] = (R)(d.w[v] * rho0);
-        t->inv_wr0[q] = (R)(1.0 / (d.w[v] * rho0));
+        t->wr0[q] = (R)(d.w[v] * rho0 / enc);
+        t->inv_wr0[q] = (R)(enc / (d.w[v] * rho0));
         t->wrd[q] = d.w[v] * rho0;
         t->shape_p[q] = shape(v);
         t->shape_m[q] = shape(v + 1);
@@ -242,6 +255,42 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
     s->aligned_rows = (p.nx % 64) == 0;
+}
+
+// 1 / D(e) of a duct's wall elements, [face][position along the face]. A
+// slot (x, alpha) whose virtual source x - e_alpha lies outside belongs to the
+// face its segment crosses first going outward from x (ties to the y face) and
+// to x's cell on that face; D(e) sums w (1 - dt/2 g.xi) over e's slots. It does
+// not depend on x along the periodic direction, and y-face (z-face) elements
+// only through z (y).
+static void duct_invd(const Dvm &d, const lbm_problem_t &p, const lbm_params_t &par,
+                      std::vector<double> &out) {
+    const int ny = p.ny, nz = p.nz;
+    const int64_t np = face_positions(p);
+    std::vector<double> D(4 * np, 0.0);
+    auto exit_time = [](int from, int v, int n) {
+        const double plane = v > 0 ? (double)n - 0.5 : -0.5;
+        return (plane - (double)from) / (double)v;
+    };
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            if (j >= d.halo && j < ny - d.halo && k >= d.halo && k < nz - d.halo) continue;
+            for (int v = 0; v < d.V; ++v) {
+                const int *e = &d.vel[3 * v];
+                const int js = j - e[1], ks = k - e[2];
+                const bool oy = js < 0 || js >= ny, oz = ks < 0 || ks >= nz;
+                if (!oy && !oz) continue;
+                bool use_z = oz;
+                if (oy && oz) use_z = exit_time(k, -e[2], nz) < exit_time(j, -e[1], ny);
+                double gx = 0;
+                for (int c = 0; c < 3; ++c) gx += par.g[c] * d.c * e[c];
+                const double shape = d.w[v] * (1.0 - 0.5 * par.dt * gx);
+                const int face = use_z ? (e[2] > 0 ? 2 : 3) : (e[1] > 0 ? 0 : 1);
+                D[face * np + (use_z ? j : k)] += shape;
+            }
+        }
+    out.assign(4 * np, 0.0);
+    for (int64_t q = 0; q < 4 * np; ++q) out[q] = D[q] > 0 ? 1.0 / D[q] : 0.0;
 }
 
 // Validated parameters and kernel tables of one problem (used by the batch).
@@ -320,6 +369,7 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
     auto *base = (unsigned char *)scratch;
     s->apart[0] = (double *)(base + L.off_a0);
     s->apart[1] = (double *)(base + L.off_a1);
+    s->invd = (double *)(base + L.off_invd);
     s->partial = (double *)(base + L.off_partial);
     s->out = (double *)(base + L.off_out);
     s->stream = (hipStream_t)stream;
@@ -330,6 +380,11 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
         fill_tables<float>(d, *prob, s->par, s->tab, s->sc);
     // zero the wall partials so a run before init is well defined
     hipError_t e = hipMemsetAsync(scratch, 0, L.off_partial, s->stream);
+    if (e == hipSuccess && prob->dim == 3) {
+        duct_invd(d, *prob, s->par, s->invd_host);
+        e = hipMemcpyAsync(s->invd, s->invd_host.data(), sizeof(double) * s->invd_host.size(),
+                           hipMemcpyHostToDevice, s->stream);
+    }
     if (e != hipSuccess) {
         delete s;
         return fail(LBM_E_DEVICE, std::string("memset: ") + hipGetErrorString(e));
@@ -355,7 +410,7 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
     if (!h || nsteps < 0) return fail(LBM_E_INVALID, "lbm_run: bad arguments");
     Solver &s = *reinterpret_cast<Solver *>(h);
     for (int64_t k = 0; k < nsteps; ++k) {
-        StepBuffers b{s.pop[s.cur], s.pop[1 - s.cur], s.apart[s.cur], s.apart[1 - s.cur]};
+        StepBuffers b{s.pop[s.cur], s.pop[1 - s.cur], s.apart[s.cur], s.apart[1 - s.cur], s.invd};
         int rc = s.L->step(b, s.tab, s.sc, s.stream, (uint32_t)s.steps);
         if (rc) return rc;
         s.cur ^= 1;
@@ -365,7 +420,8 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
 }
 
 static int observe_impl(Solver &s, double *rho_dev, double *u_dev, double *mdot, double *mass) {
-    int rc = s.L->observe(s.pop[s.cur], s.apart[s.cur], rho_dev, u_dev, s.partial, s.tab, s.sc, s.stream);
+    int rc = s.L->observe(s.pop[s.cur], s.apart[s.cur], s.invd, rho_dev, u_dev, s.partial, s.tab,
+                          s.sc, s.stream);
     if (rc) return rc;
     if (!mdot && !mass) return LBM_OK;
     rc = launch_finalize(s.partial, observe_blocks(s.nodes), s.out, s.stream);

@@ -18,8 +18,13 @@ namespace lbm {
 //   F64    : fbar in double
 //   F32    : d = fbar - w rho0 in float
 //   F32RAW : fbar in float
-//   F16DEV : d / (w rho0) in half, stochastic rounding in time steps
+//   F16DEV : kF16Scale d / (w rho0) in half, stochastic rounding in time steps
 // ---------------------------------------------------------------------------
+// The scale keeps small deviations (a flow started from rest, Ma ~ 1e-3) in
+// half's normal range, where stochastic rounding is exact and unbiased; below
+// it the conversion rounds to nearest, which biases a uniform field. It bounds
+// |d / (w rho0)| by 65504 / 1024 = 64. The tables' wr0 / inv_wr0 carry it.
+constexpr double kF16Scale = 1024.0;
 template <Storage S>
 struct St;
 template <>
@@ -94,7 +99,7 @@ __device__ __forceinline__ typename St<S>::T encode_dev(typename St<S>::R d,
 template <Storage S>
 __device__ __forceinline__ double stored_value(typename St<S>::T v, double wrd) {
     if constexpr (S == Storage::F16DEV)
-        return wrd * (1.0 + (double)(float)v);
+        return wrd * (1.0 + (double)(float)v * (1.0 / kF16Scale));
     else if constexpr (S == Storage::F32)
         return wrd + (double)v;
     else

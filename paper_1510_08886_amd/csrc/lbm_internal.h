@@ -38,8 +38,8 @@ struct PairTable {
     R xi[kMaxPairs][3];             // c * e_p
     R qq[kMaxPairs][6];             // xi_x^2, xi_y^2, xi_z^2, xi_x xi_y, xi_x xi_z, xi_y xi_z
     R w[kMaxPairs];                 // pair weight
-    R wr0[kMaxPairs];               // w * rho0
-    R inv_wr0[kMaxPairs];           // 1 / (w rho0) (deviation storage)
+    R wr0[kMaxPairs];               // w * rho0 (F16DEV: w * rho0 / 1024)
+    R inv_wr0[kMaxPairs];           // 1 / wr0 (deviation storage)
     double wrd[kMaxPairs];          // w * rho0 in double
     double shape_p[kMaxPairs];      // w (1 - dt/2 g.xi) for +e_p  (wall slots)
     double shape_m[kMaxPairs];      // w (1 + dt/2 g.xi) for -e_p
@@ -58,7 +58,7 @@ struct StepScalars {
     R g[3], half_dt_g[3];           // g and dt/2 g
     R cn[6];                        // 1/n! for the Hermite terms, 0 beyond N
     double rho0d;
-    double invD[4];                 // 1 / D(e) per face (uniform along a face)
+    double invD[4];                 // 1 / D(e) per face (2D: uniform along a face)
     double hgc;                     // dt/2 * g_x * c: wall shape w (1 - hgc e_x)
     double kA[4][8];                // per face and wall row r: sum of w rho0 over the
                                     // velocities leaving through the face from row r
@@ -77,6 +77,7 @@ struct StepBuffers {
     void *dst;
     const double *a_cur;            // wall-flux partials of src  [face][halo][elements]
     double *a_next;                 // wall-flux partials of dst
+    const double *invd;             // 3D: 1 / D(e) per face and position along it
 };
 
 // Launchers (instantiated in the .hip translation unit).
@@ -84,8 +85,8 @@ struct Launch {
     int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, uint32_t step);
     int (*init)(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
                 const void *sc, hipStream_t, uint32_t step);
-    int (*observe)(const void *src, const double *a_cur, double *rho, double *u, double *partial,
-                   const void *tab, const void *sc, hipStream_t);
+    int (*observe)(const void *src, const double *a_cur, const double *invd, double *rho, double *u,
+                   double *partial, const void *tab, const void *sc, hipStream_t);
     int (*exportp)(const void *src, double *out, const void *tab, const void *sc, hipStream_t);
     int (*importp)(void *dst, double *a_out, const double *in, const void *tab, const void *sc,
                    hipStream_t, uint32_t step);

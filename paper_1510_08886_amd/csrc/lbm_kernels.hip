@@ -223,8 +223,9 @@ struct L2 {
                            a_out, rho, u, t, s, stp);
         return hip_ok(hipGetLastError(), "init kernel launch");
     }
-    static int observe(const void *src, const double *a_cur, double *rho, double *u,
-                       double *partial, const void *tab, const void *sc, hipStream_t st) {
+    static int observe(const void *src, const double *a_cur, const double * /*invd*/, double *rho,
+                       double *u, double *partial, const void *tab, const void *sc,
+                       hipStream_t st) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_observe2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,

@@ -1,0 +1,457 @@
+// HIP kernels for gfx950: the fused pull-stream + diffuse Maxwell wall + BGK
+// update (Eq. nm.8) of a 3D duct: x periodic, walls normal to y and z.
+//
+// Node n = (k * ny + j) * nx + i; populations in 64-node blocks (aos_base).
+// Pull sources are clamped into the duct in y and z so every load is valid;
+// the populations whose source lies outside are replaced by the diffuse-wall
+// populations rho_eff w (1 - dt/2 g.xi) of Eqs. nm.14 / nm.15.
+//
+// Wall elements: an unknown slot (x, alpha), whose virtual source x - e_alpha
+// lies outside, and the absorbed population (x, -alpha) cross the same
+// segment; both belong to the wall cell of the fluid node x on the face the
+// segment crosses first going outward (ties to the y face). y faces have
+// elements (k, i), z faces (j, i). rho_eff(e) = A(e) / D(e): A(e) is the FP64
+// sum of the post-collision populations that left through e, kept per wall
+// row (distance of the node from the face) and summed by the consumer; D(e)
+// depends only on the element's position along the face (k or j) and is
+// tabulated on the host, since slots near the duct's edges may belong to the
+// other face.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+enum : int { kYLo = 0, kYHi = 1, kZLo = 2, kZHi = 3 };
+
+template <typename R>
+struct Moments3D {
+    R drho, rho, ux, uy, uz, sxx, syy, szz, sxy, sxz, syz;
+};
+
+template <class SET, typename R>
+__device__ __forceinline__ Moments3D<R> moments3d(const R (&d)[SET::V], const StepScalars<R> &s,
+                                                  R c) {
+    constexpr int NR = SET::NR;
+    R drho = NR ? d[0] : R(0);
+    R jx = 0, jy = 0, jz = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
+        const R dp = d[NR + 2 * p], dm = d[NR + 2 * p + 1];
+        const R sum = dp + dm, dif = dp - dm;
+        drho += sum;
+        jx = addk<ex>(jx, dif);
+        jy = addk<ey>(jy, dif);
+        jz = addk<ez>(jz, dif);
+        sxx = addk<ex * ex>(sxx, sum);
+        syy = addk<ey * ey>(syy, sum);
+        szz = addk<ez * ez>(szz, sum);
+        sxy = addk<ex * ey>(sxy, sum);
+        sxz = addk<ex * ez>(sxz, sum);
+        syz = addk<ey * ez>(syz, sum);
+    });
+    Moments3D<R> m;
+    const R c2 = c * c;
+    m.drho = drho;
+    m.rho = s.rho0 + drho;
+    const R inv = R(1) / m.rho;
+    m.ux = fma(s.half_dt_g[0], m.rho, jx * c) * inv;
+    m.uy = jy * c * inv;
+    m.uz = jz * c * inv;
+    m.sxx = sxx * c2;
+    m.syy = syy * c2;
+    m.szz = szz * c2;
+    m.sxy = sxy * c2;
+    m.sxz = sxz * c2;
+    m.syz = syz * c2;
+    return m;
+}
+
+// equilibrium (scalar Hermite recurrence) + force of Eq. nm.4 (g along x) +
+// BGK relaxation of the modified populations, on deviations d = fbar - w rho0
+template <class SET, typename R>
+__device__ __forceinline__ void relax3d(R (&d)[SET::V], const PairTable<R> &t,
+                                        const StepScalars<R> &s, R c) {
+    constexpr int NR = SET::NR;
+    const auto m = moments3d<SET, R>(d, s, c);
+    const R drho = m.drho, rho = m.rho, ux = m.ux, uy = m.uy, uz = m.uz;
+    const R gx = s.g[0];
+    // a2 = Pi(f) - rho I from fbar by inverting Eq. nm.7 (deviation form)
+    const R hr = s.h * rho;
+    const R htr = hr * s.tau;
+    const R i1h = s.inv1h;
+    const R a2xx = (m.sxx - drho + hr * ux * ux + R(2) * htr * gx * ux) * i1h;
+    const R a2yy = (m.syy - drho + hr * uy * uy) * i1h;
+    const R a2zz = (m.szz - drho + hr * uz * uz) * i1h;
+    const R a2xy = (m.sxy + hr * ux * uy + htr * gx * uy) * i1h;
+    const R a2xz = (m.sxz + hr * ux * uz + htr * gx * uz) * i1h;
+    const R a2yz = (m.syz + hr * uy * uz) * i1h;
+    const R tra2 = a2xx + a2yy + a2zz;
+    const R c2 = c * c;
+    const R qxx = a2xx * c2, qyy = a2yy * c2, qzz = a2zz * c2;
+    const R qxy = R(2) * a2xy * c2, qxz = R(2) * a2xz * c2, qyz = R(2) * a2yz * c2;
+    const R gxc = gx * c;
+    const R hxc = a2xx * gxc, hyc = a2xy * gxc, hzc = a2xz * gxc;   // (a2 g) . xi
+    const R uxc = ux * c, uyc = uy * c, uzc = uz * c;
+    const R u2 = ux * ux + uy * uy + uz * uz;
+    const R u2_3 = R(3) * u2;
+    const R ug = ux * gx;
+    const R tr = s.tau * rho;
+    const R trgxc = tr * gxc;
+    const R half_tau = R(0.5) * s.tau;
+    const R rc2 = rho * s.cn[2], rc3 = rho * s.cn[3], rc4 = rho * s.cn[4];
+    const R om = s.omega;
+    const R even0 = drho - tr * ug;
+    if constexpr (NR) {
+        const R even = fma(rc2, -u2, fma(rc4, u2_3 * u2, even0));
+        d[0] = fma(om, fma(t.w0, even, -d[0]), d[0]);
+    }
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
+        const R ue = lin3<ex, ey, ez>(uxc, uyc, uzc);
+        const R ue2 = ue * ue;
+        const R P2 = ue2 - u2;
+        const R P3 = ue * (ue2 - u2_3);
+        const R P4 = fma(ue, P3, -u2_3 * P2);
+        R even = fma(rc2, P2, fma(rc4, P4, even0));
+        R odd = fma(rc3, P3, rho * ue);
+        if constexpr (ex != 0) {
+            even = fma(mulk<ex>(trgxc), ue, even);
+            // a2 : xi xi (the off-diagonal terms carry their factor 2)
+            R q = lin3<ex * ex, ey * ey, ez * ez>(qxx, qyy, qzz);
+            q = addk<ex * ey>(q, qxy);
+            q = addk<ex * ez>(q, qxz);
+            q = addk<ey * ez>(q, qyz);
+            odd = fma(mulk<ex>(gxc), fma(half_tau, q - tra2, tr), odd);
+        }
+        if constexpr (ex != 0 || ey != 0 || ez != 0) odd = fma(-s.tau, lin3<ex, ey, ez>(hxc, hyc, hzc), odd);
+        const R w = t.w[p];
+        R &dp = d[NR + 2 * p];
+        R &dm = d[NR + 2 * p + 1];
+        dp = fma(om, fma(w, even + odd, -dp), dp);
+        dm = fma(om, fma(w, even - odd, -dm), dm);
+    });
+}
+
+// fraction of the step at which a particle at coordinate `from`, moving with
+// integer velocity component v != 0, crosses the wall plane ahead of it
+__device__ __forceinline__ double exit_time(int from, int v, int n) {
+    const double plane = v > 0 ? (double)n - 0.5 : -0.5;
+    return (plane - (double)from) / (double)v;
+}
+
+// face of the segment from node (j, k) along (vy, vz) to a point outside in y
+// (oy) and/or z (oz): the first one crossed, ties to y
+__device__ __forceinline__ int first_face(int j, int k, int vy, int vz, bool oy, bool oz, int ny,
+                                          int nz) {
+    bool use_z = oz;
+    if (oy && oz) use_z = exit_time(k, vz, nz) < exit_time(j, vy, ny);
+    if (use_z) return vz < 0 ? kZLo : kZHi;
+    return vy < 0 ? kYLo : kYHi;
+}
+
+// ---------------------------------------------------------------------------
+// gather
+// ---------------------------------------------------------------------------
+template <class SET, Storage S>
+__device__ __forceinline__ void issue3d(const typename St<S>::T *__restrict__ src,
+                                        const StepScalars<typename St<S>::R> &s, int i, int j,
+                                        int k, typename St<S>::T (&raw)[SET::V]) {
+    constexpr int NR = SET::NR, H = SET::H, HN = SET::HN, V = SET::V;
+    const int nx = s.nx, ny = s.ny, nz = s.nz;
+    uint32_t xo[2 * H + 1];
+#pragma unroll
+    for (int q = -H; q <= H; ++q) xo[q + H] = (uint32_t)wrap_col(i - q, nx, H);
+    int ry[2 * HN + 1], rz[2 * HN + 1];
+#pragma unroll
+    for (int q = -HN; q <= HN; ++q) {
+        ry[q + HN] = min(max(j - q, 0), ny - 1);
+        rz[q + HN] = min(max(k - q, 0), nz - 1);
+    }
+    if constexpr (NR) raw[0] = src[aos_base<V>(((uint32_t)k * ny + j) * nx + i)];
+    if (s.aligned_rows) {
+        const uint32_t rowstride = (uint32_t)nx * V;
+        uint32_t cp[2 * H + 1];
+#pragma unroll
+        for (int q = 0; q < 2 * H + 1; ++q) cp[q] = (xo[q] >> 6) * (uint32_t)(64 * V) + (xo[q] & 63u);
+        for_pairs<SET::NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
+            const uint32_t rowp = (uint32_t)rz[ez + HN] * ny + ry[ey + HN];
+            const uint32_t rowm = (uint32_t)rz[-ez + HN] * ny + ry[-ey + HN];
+            raw[NR + 2 * p] = src[rowp * rowstride + cp[ex + H] + 64 * (NR + 2 * p)];
+            raw[NR + 2 * p + 1] = src[rowm * rowstride + cp[-ex + H] + 64 * (NR + 2 * p + 1)];
+        });
+    } else {
+        for_pairs<SET::NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
+            const uint32_t np_ = ((uint32_t)rz[ez + HN] * ny + ry[ey + HN]) * nx + xo[ex + H];
+            const uint32_t nm_ = ((uint32_t)rz[-ez + HN] * ny + ry[-ey + HN]) * nx + xo[-ex + H];
+            raw[NR + 2 * p] = src[aos_base<V>(np_) + 64 * (NR + 2 * p)];
+            raw[NR + 2 * p + 1] = src[aos_base<V>(nm_) + 64 * (NR + 2 * p + 1)];
+        });
+    }
+}
+
+template <class SET, Storage S>
+__device__ __forceinline__ void complete3d(const typename St<S>::T (&raw)[SET::V],
+                                           const double *__restrict__ a_cur,
+                                           const double *__restrict__ invd,
+                                           const PairTable<typename St<S>::R> &t,
+                                           const StepScalars<typename St<S>::R> &s, int i, int j,
+                                           int k, typename St<S>::R (&d)[SET::V]) {
+    using R = typename St<S>::R;
+    constexpr int NR = SET::NR, HN = SET::HN;
+    const int nx = s.nx, ny = s.ny, nz = s.nz;
+    if constexpr (NR) d[0] = decode_dev<S>(raw[0], t.wr00);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        d[NR + 2 * p] = decode_dev<S>(raw[NR + 2 * p], t.wr0[p]);
+        d[NR + 2 * p + 1] = decode_dev<S>(raw[NR + 2 * p + 1], t.wr0[p]);
+    });
+    const bool ylo = j < HN, yhi = j >= ny - HN, zlo = k < HN, zhi = k >= nz - HN;
+    if (!(ylo || yhi || zlo || zhi)) return;
+    // rho_eff of this node's element on each face it is next to
+    const int64_t fs = (int64_t)HN * max(nz, ny) * nx;
+    const int64_t ey_ = (int64_t)k * nx + i, ez_ = (int64_t)j * nx + i;
+    const int64_t dstride = max(nz, ny);
+    double reff[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const bool near = f == kYLo ? ylo : f == kYHi ? yhi : f == kZLo ? zlo : zhi;
+        if (!near) continue;
+        const int64_t el = f < 2 ? ey_ : ez_;
+        const int64_t epl = f < 2 ? (int64_t)nz * nx : (int64_t)ny * nx;
+        double a = 0.0;
+        for (int r = 0; r < HN; ++r) a += a_cur[f * fs + r * epl + el];
+        reff[f] = a * invd[f * dstride + (f < 2 ? k : j)];
+    }
+    const double rho0 = s.rho0d, hgc = s.hgc;
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
+        if constexpr (ey != 0 || ez != 0) {
+            const double wd = (double)t.w[p];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int sy = m ? -ey : ey, sz = m ? -ez : ez, sx = m ? -ex : ex;
+                const int js = j - sy, ks = k - sz;
+                const bool oy = js < 0 || js >= ny, oz = ks < 0 || ks >= nz;
+                if (oy || oz) {
+                    const int f = first_face(j, k, -sy, -sz, oy, oz, ny, nz);
+                    d[NR + 2 * p + m] = (R)(wd * (reff[f] * (1.0 - hgc * sx) - rho0));
+                }
+            }
+        }
+    });
+}
+
+template <class SET, Storage S>
+__device__ __forceinline__ void wall_partials3d(const typename St<S>::T (&v)[SET::V],
+                                                const PairTable<typename St<S>::R> &t,
+                                                const StepScalars<typename St<S>::R> &s, int i,
+                                                int j, int k, double *__restrict__ a_next) {
+    constexpr int NR = SET::NR, HN = SET::HN;
+    const int nx = s.nx, ny = s.ny, nz = s.nz;
+    const bool ylo = j < HN, yhi = j >= ny - HN, zlo = k < HN, zhi = k >= nz - HN;
+    if (!(ylo || yhi || zlo || zhi)) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int ey = SET::EY[p], ez = SET::EZ[p];
+        if constexpr (ey != 0 || ez != 0) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int sy = m ? -ey : ey, sz = m ? -ez : ez;
+                const int jd = j + sy, kd = k + sz;
+                const bool oy = jd < 0 || jd >= ny, oz = kd < 0 || kd >= nz;
+                if (oy || oz) {
+                    const int f = first_face(j, k, sy, sz, oy, oz, ny, nz);
+                    acc[f] += stored_value<S>(v[NR + 2 * p + m], t.wrd[p]);
+                }
+            }
+        }
+    });
+    const int64_t fs = (int64_t)HN * max(nz, ny) * nx;
+    const int64_t epy = (int64_t)nz * nx, epz = (int64_t)ny * nx;
+    if (ylo) a_next[kYLo * fs + (int64_t)j * epy + (int64_t)k * nx + i] = acc[kYLo];
+    if (yhi) a_next[kYHi * fs + (int64_t)(ny - 1 - j) * epy + (int64_t)k * nx + i] = acc[kYHi];
+    if (zlo) a_next[kZLo * fs + (int64_t)k * epz + (int64_t)j * nx + i] = acc[kZLo];
+    if (zhi) a_next[kZHi * fs + (int64_t)(nz - 1 - k) * epz + (int64_t)j * nx + i] = acc[kZHi];
+}
+
+template <class SET, Storage S, bool SRND>
+__device__ __forceinline__ void scatter3d(typename St<S>::T *__restrict__ dst,
+                                          double *__restrict__ a_next,
+                                          const PairTable<typename St<S>::R> &t,
+                                          const StepScalars<typename St<S>::R> &s, int i, int j,
+                                          int k, const typename St<S>::R (&d)[SET::V],
+                                          uint32_t step) {
+    using T = typename St<S>::T;
+    const uint32_t n = ((uint32_t)k * s.ny + j) * s.nx + i;
+    T v[SET::V];
+    encode_all<SET, S, SRND>(d, t, n, step, v);
+    T *out = dst + aos_base<SET::V>(n);
+#pragma unroll
+    for (int a = 0; a < SET::V; ++a) out[64 * a] = v[a];
+    wall_partials3d<SET, S>(v, t, s, i, j, k, a_next);
+}
+
+__device__ __forceinline__ void node_ijk(uint32_t n, int nx, int ny, int &i, int &j, int &k) {
+    const uint32_t row = n / (uint32_t)nx;
+    i = (int)(n - row * nx);
+    k = (int)(row / (uint32_t)ny);
+    j = (int)(row - (uint32_t)k * ny);
+}
+
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t,
+                                                StepScalars<typename St<S>::R> s, uint32_t step) {
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
+    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    int i, j, k;
+    node_ijk(n, s.nx, s.ny, i, j, k);
+    T raw[SET::V];
+    issue3d<SET, S>((const T *)b.src, s, i, j, k, raw);
+    R d[SET::V];
+    complete3d<SET, S>(raw, b.a_cur, b.invd, t, s, i, j, k, d);
+    relax3d<SET, R>(d, t, s, t.c);
+    scatter3d<SET, S, true>((T *)b.dst, b.a_next, t, s, i, j, k, d, step);
+}
+
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_observe3d(const void *src, const double *a_cur,
+                                                   const double *invd, double *rho_out,
+                                                   double *u_out, double *partial,
+                                                   PairTable<typename St<S>::R> t,
+                                                   StepScalars<typename St<S>::R> s) {
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    double ux_d = 0.0, rho_d = 0.0;
+    if (n < (uint32_t)s.nodes) {
+        int i, j, k;
+        node_ijk(n, s.nx, s.ny, i, j, k);
+        T raw[SET::V];
+        issue3d<SET, S>((const T *)src, s, i, j, k, raw);
+        R d[SET::V];
+        complete3d<SET, S>(raw, a_cur, invd, t, s, i, j, k, d);
+        const auto m = moments3d<SET, R>(d, s, t.c);
+        rho_d = s.rho0d + (double)m.drho;
+        ux_d = (double)m.ux;
+        if (rho_out) rho_out[n] = rho_d;
+        if (u_out) {
+            u_out[3 * n] = (double)m.ux;
+            u_out[3 * n + 1] = (double)m.uy;
+            u_out[3 * n + 2] = (double)m.uz;
+        }
+    }
+    block_sum2(ux_d, rho_d, partial);
+}
+
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_init3d(void *dst, double *a_out, const double *rho_in,
+                                                const double *u_in,
+                                                PairTable<typename St<S>::R> t,
+                                                StepScalars<typename St<S>::R> s, uint32_t step) {
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    int i, j, k;
+    node_ijk(n, s.nx, s.ny, i, j, k);
+    const double rho = rho_in ? rho_in[n] : s.rho0d;
+    R ux = 0, uy = 0, uz = 0;
+    if (u_in) {
+        ux = (R)u_in[3 * n];
+        uy = (R)u_in[3 * n + 1];
+        uz = (R)u_in[3 * n + 2];
+    }
+    R d[SET::V];
+    equilibrium_dev<SET, R>(t, s, rho, ux, uy, uz, d);
+    scatter3d<SET, S, false>((T *)dst, a_out, t, s, i, j, k, d, step);
+}
+
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_import3d(void *dst, double *a_out, const double *in,
+                                                  PairTable<typename St<S>::R> t,
+                                                  StepScalars<typename St<S>::R> s, uint32_t step) {
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    int i, j, k;
+    node_ijk(n, s.nx, s.ny, i, j, k);
+    R d[SET::V];
+    import_node<SET, R>(in, t, (uint32_t)s.nodes, n, d);
+    scatter3d<SET, S, false>((T *)dst, a_out, t, s, i, j, k, d, step);
+}
+
+template <class SET, Storage S>
+struct L3 {
+    using R = typename St<S>::R;
+    static int step(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
+                    uint32_t stp) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        hipLaunchKernelGGL((k_step3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, b, t,
+                           s, stp);
+        return hip_ok(hipGetLastError(), "3D step kernel launch");
+    }
+    static int init(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
+                    const void *sc, hipStream_t st, uint32_t stp) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        hipLaunchKernelGGL((k_init3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, dst,
+                           a_out, rho, u, t, s, stp);
+        return hip_ok(hipGetLastError(), "3D init kernel launch");
+    }
+    static int observe(const void *src, const double *a_cur, const double *invd, double *rho,
+                       double *u, double *partial, const void *tab, const void *sc,
+                       hipStream_t st) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        hipLaunchKernelGGL((k_observe3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,
+                           src, a_cur, invd, rho, u, partial, t, s);
+        return hip_ok(hipGetLastError(), "3D observe kernel launch");
+    }
+    static int exportp(const void *src, double *out, const void *tab, const void *sc,
+                       hipStream_t st) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        hipLaunchKernelGGL((k_export<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, src,
+                           out, t, s);
+        return hip_ok(hipGetLastError(), "export kernel launch");
+    }
+    static int importp(void *dst, double *a_out, const double *in, const void *tab, const void *sc,
+                       hipStream_t st, uint32_t stp) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        hipLaunchKernelGGL((k_import3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,
+                           dst, a_out, in, t, s, stp);
+        return hip_ok(hipGetLastError(), "3D import kernel launch");
+    }
+    static constexpr Launch table{&step, &init, &observe, &exportp, &importp};
+};
+
+#define LBM_3D(SET)                                                           \
+    {SET::ID, Storage::F64, &L3<SET, Storage::F64>::table},                   \
+        {SET::ID, Storage::F32, &L3<SET, Storage::F32>::table},               \
+        {SET::ID, Storage::F32RAW, &L3<SET, Storage::F32RAW>::table},         \
+        {SET::ID, Storage::F16DEV, &L3<SET, Storage::F16DEV>::table}
+
+const Launch *find_launch_3d(int set_id, Storage st) {
+    static const Entry entries[] = {LBM_3D(SetD3V39), LBM_3D(SetD3V15)};
+    for (const auto &e : entries)
+        if (e.id == set_id && e.s == st) return e.l;
+    return nullptr;
+}
+
+}  // namespace lbm

@@ -7,6 +7,7 @@
 namespace lbm {
 
 const Launch *find_launch_2d(int set_id, Storage st);
+const Launch *find_launch_3d(int set_id, Storage st);
 
 int observe_blocks(int64_t nodes) { return (int)blocks_for(nodes); }
 
@@ -65,7 +66,7 @@ const std::vector<VelSetInfo> &velocity_sets() {
 
 const Launch *find_launch(int set_id, Storage s) {
     if (const Launch *l = find_launch_2d(set_id, s)) return l;
-    return nullptr;
+    return find_launch_3d(set_id, s);
 }
 
 }  // namespace lbm

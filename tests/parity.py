@@ -12,18 +12,31 @@ def oracle_perm(lib_dvm, o_dvm):
     return np.array([index[tuple(int(x) for x in e)] for e in lib_dvm.velocities])
 
 
+# velocity sets with compiled kernels that are not among the named ones:
+# (dim, generators, quadrature order); both sides solve for c and the weights
+EXTRA_SETS = {"D3V15": (3, [(0, 0, 0), (2, 0, 0), (1, 1, 1)], 5)}
+
+
+def dvm_pair(name):
+    from paper_1510_08886_amd import lbm
+
+    if name in EXTRA_SETS:
+        dim, gens, Q = EXTRA_SETS[name]
+        return lbm.Dvm.solve(dim, gens, Q), odvm.solve_dvm(dim, gens, Q)
+    return lbm.Dvm.named(name), odvm.named_dvm(name)
+
+
 def make_pair(name, N, nx, ny, nz=1, kn=0.1, ma=1e-3, storage="f64", rho=None, u=None,
               walls_z=False):
     import torch
     from paper_1510_08886_amd import lbm
 
-    spec = lbm.NAMED_DVMS[name]
-    d = lbm.Dvm.named(name)
-    prob = lbm.Problem(dim=spec["dim"], nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, hermite_order=N,
+    d, od = dvm_pair(name)
+    prob = lbm.Problem(dim=d.dim, nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, hermite_order=N,
                        storage=storage)
     g = lbm.Solver(d, prob)
-    o = stepper.OracleSolver(odvm.named_dvm(name), nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, N=N,
-                             walls_z=walls_z or spec["dim"] == 3)
+    o = stepper.OracleSolver(od, nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, N=N,
+                             walls_z=walls_z or d.dim == 3)
     if rho is None:
         g.init()
         o.init()

@@ -295,3 +295,18 @@ def test_bruteforce_python_matches_c_oracle(oracle_lib, name, N):
             n = j * nx + i
             for a, e in enumerate(vels):
                 assert abs(f[(i, j, e)] - s.f[n, a]) < 1e-15
+
+
+def test_duct_golden_file_is_consistent():
+    """The stored oracle duct run (tests/golden/duct_d3v39_mdot.txt): mass of
+    the 256 x 256 column stays rho0 * nodes, and the flow started from rest
+    accelerates monotonically over the first 500 steps."""
+    from pathlib import Path
+    rows = [l.split() for l in (Path(__file__).resolve().parent / "golden" / "duct_d3v39_mdot.txt")
+            .read_text().splitlines() if l and not l.startswith("#")]
+    steps = [int(r[0]) for r in rows]
+    mdot = [float(r[1]) for r in rows]
+    mass = [float(r[2]) for r in rows]
+    assert steps == list(range(50, 501, 50))
+    assert all(abs(m - 65536.0) <= 1e-12 * 65536.0 for m in mass)
+    assert all(b > a for a, b in zip(mdot, mdot[1:]))
