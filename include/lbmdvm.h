@@ -112,6 +112,31 @@ int lbm_dvm_destroy(lbm_dvm_t *dvm);
  * and lattice speed; vel, w and c may be NULL (size query). Host arrays. */
 int lbm_dvm_info(const lbm_dvm_t *dvm, int *V, int32_t *vel, double *w, double *c);
 
+/* ---- wall-moment diagnostics (Section IV.B-C) ----------------------------- */
+
+/* Summary of how well a DVM reproduces the diffuse Maxwell wall. */
+typedef struct {
+    int n_components;       /* L: non-trivial wall moments of rank <= Q (Eq. nontriv) */
+    int lambda_order;       /* wall accuracy order (Eq. defLambda); -1 if W itself is inexact */
+    uint64_t lambda_index;  /* wall accuracy index (Eq. defbin): bit k set when the
+                               (k+1)-th non-trivial moment is exact */
+    double sigma_sigma;     /* e^-n weighted mean of |sigma| over the L moments (Eq. sigmaSigma) */
+} lbm_wall_report_t;
+
+/* Equilibrium wall moments of a DVM (Eqs. defW, Wscalar) against their
+ * quadrature over the velocities leaving the wall into the fluid (Eq. wallQuad),
+ * for the wall whose inward normal is +e along velocity component normal_axis
+ * (0 <= normal_axis < dim; the other components are the tangential x and y in
+ * increasing order). The L non-trivial moments are listed in the order of Eqs.
+ * defT / defb: exps[3k..3k+2] = (m_x, m_y, m_z), the exact moment w_exact[k],
+ * its quadrature w_dvm[k] and sigma[k] = (w_dvm - w_exact) / w_exact (the sign
+ * of the paper's tables). A moment counts as exact to a relative 1e-10. The
+ * arrays (host, `cap` entries, any may be NULL) need cap >= L, else
+ * LBM_E_NO_MEMORY; query L with all arrays NULL. LBM_E_UNSUPPORTED if L > 64.
+ * Host only. */
+int lbm_dvm_wall_errors(const lbm_dvm_t *dvm, int normal_axis, int cap, int32_t *exps,
+                        double *w_exact, double *w_dvm, double *sigma, lbm_wall_report_t *report);
+
 /* ---- solver --------------------------------------------------------------- */
 
 /* Derived scalars for a problem (pure host). */

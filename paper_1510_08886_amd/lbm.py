@@ -56,6 +56,11 @@ class ResultC(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("mdot", ctypes.c_double), ("kn", ctypes.c_double)]
 
 
+class WallReportC(ctypes.Structure):
+    _fields_ = [("n_components", ctypes.c_int), ("lambda_order", ctypes.c_int),
+                ("lambda_index", ctypes.c_uint64), ("sigma_sigma", ctypes.c_double)]
+
+
 class BatchStatsC(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int), ("queued", ctypes.c_int), ("done", ctypes.c_int),
                 ("threads", ctypes.c_int), ("quantum", ctypes.c_int), ("launches", ctypes.c_int64),
@@ -79,6 +84,7 @@ SIGNATURES = {
     "lbm_dvm_create": ([_I, _I, _I32P, _DP, _D, _I, ctypes.POINTER(_P)], _I),
     "lbm_dvm_destroy": ([_P], _I),
     "lbm_dvm_info": ([_P, _IP, _I32P, _DP, _DP], _I),
+    "lbm_dvm_wall_errors": ([_P, _I, _I, _I32P, _DP, _DP, _DP, ctypes.POINTER(WallReportC)], _I),
     "lbm_params": ([_P, ctypes.POINTER(ProblemC), ctypes.POINTER(ParamsC)], _I),
     "lbm_state_bytes": ([_P, ctypes.POINTER(ProblemC), _SZP, _SZP], _I),
     "lbm_solver_create": ([_P, ctypes.POINTER(ProblemC), _P, _P, _P, ctypes.c_size_t, _P,
@@ -180,6 +186,23 @@ class Dvm:
         d.name = name
         d.default_N = spec["N"]
         return d
+
+    def wall_errors(self, normal_axis: int | None = None) -> dict:
+        """Equilibrium wall moments and their errors (lbm_dvm_wall_errors)."""
+        ax = self.dim - 1 if normal_axis is None else int(normal_axis)
+        rep = WallReportC()
+        check(lib().lbm_dvm_wall_errors(self._h, ax, 0, None, None, None, None, ctypes.byref(rep)),
+              "lbm_dvm_wall_errors")
+        L = rep.n_components
+        ex = np.zeros(3 * L, dtype=np.int32)
+        we, wd, sg = np.zeros(L), np.zeros(L), np.zeros(L)
+        check(lib().lbm_dvm_wall_errors(self._h, ax, L, ex.ctypes.data_as(_I32P),
+                                        we.ctypes.data_as(_DP), wd.ctypes.data_as(_DP),
+                                        sg.ctypes.data_as(_DP), ctypes.byref(rep)),
+              "lbm_dvm_wall_errors")
+        return dict(components=[tuple(int(v) for v in ex[3 * k:3 * k + 3]) for k in range(L)],
+                    W=we, W_dvm=wd, sigma=sg, sigma_sigma=rep.sigma_sigma,
+                    lambda_index=int(rep.lambda_index), lambda_order=rep.lambda_order)
 
     def __del__(self):
         h = getattr(self, "_h", None)
