@@ -100,6 +100,7 @@ int validate(const Dvm &d, const lbm_problem_t &p) {
         hn = std::max(hn, std::abs(d.vel[3 * v + 1]));
         if (p.dim == 3) hn = std::max(hn, std::abs(d.vel[3 * v + 2]));
     }
+    if (hn > kMaxWallRows) return fail(LBM_E_UNSUPPORTED, "wall-normal velocity components above 16");
     if (p.ny < hn || (p.dim == 3 && p.nz < hn))
         return fail(LBM_E_INVALID, "ny (and nz) must be at least the largest wall-normal |e|");
     if (p.hermite_order < 2 || p.hermite_order > (d.Q + 1) / 2)
@@ -164,7 +165,6 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     std::memset(tab, 0, sizeof(PairTable<R>));
     std::memset(sc, 0, sizeof(StepScalars<R>));
     const double rho0 = p.rho0;
-    const int nx = p.nx;
     auto shape = [&](int v) {
         double gx = 0;
         for (int k = 0; k < 3; ++k) gx += par.g[k] * d.c * d.vel[3 * v + k];
@@ -177,32 +177,14 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
         t->wr00 = (R)(d.w[0] * rho0 / enc);
         t->inv_wr00 = (R)(enc / (d.w[0] * rho0));
         t->wrd0 = d.w[0] * rho0;
-        t->shape0 = shape(0);
     }
     const int np = d.V / 2;
     for (int q = 0; q < np; ++q) {
         const int v = d.n_rest + 2 * q;
-        const int *e = &d.vel[3 * v];
-        double xi[3];
-        for (int k = 0; k < 3; ++k) xi[k] = d.c * e[k];
-        for (int k = 0; k < 3; ++k) t->xi[q][k] = (R)xi[k];
-        t->qq[q][0] = (R)(xi[0] * xi[0]);
-        t->qq[q][1] = (R)(xi[1] * xi[1]);
-        t->qq[q][2] = (R)(xi[2] * xi[2]);
-        t->qq[q][3] = (R)(xi[0] * xi[1]);
-        t->qq[q][4] = (R)(xi[0] * xi[2]);
-        t->qq[q][5] = (R)(xi[1] * xi[2]);
         t->w[q] = (R)d.w[v];
         t->wr0[q] = (R)(d.w[v] * rho0 / enc);
         t->inv_wr0[q] = (R)(enc / (d.w[v] * rho0));
         t->wrd[q] = d.w[v] * rho0;
-        t->shape_p[q] = shape(v);
-        t->shape_m[q] = shape(v + 1);
-        t->ex[q] = e[0];
-        t->ey[q] = e[1];
-        t->ez[q] = e[2];
-        t->exm[q] = ((e[0] % nx) + nx) % nx;
-        t->exmn[q] = ((-e[0] % nx) + nx) % nx;
     }
     s->rho0 = (R)rho0;
     s->rho0d = rho0;
@@ -236,7 +218,7 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->hgc = 0.5 * par.dt * par.g[0] * d.c;
     // w rho0 of the populations that leave through each face from wall row r
     const bool dev_storage = p.storage == LBM_F32 || p.storage == LBM_F16DEV;
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < kMaxWallRows; ++r) {
         double k[4] = {0, 0, 0, 0};
         for (int v = 0; v < d.V; ++v) {
             const int ey = d.vel[3 * v + 1], ez = d.vel[3 * v + 2];

@@ -29,25 +29,20 @@ int fail(int code, const std::string &msg);
 // ---------------------------------------------------------------------------
 // kernel-side tables, passed by value as kernel arguments
 // ---------------------------------------------------------------------------
-constexpr int kMaxPairs = 20;       // up to V = 41
+constexpr int kMaxPairs = 64;       // up to V = 129
+constexpr int kMaxWallRows = 16;    // largest wall-normal |e| with compiled kernels
 
 // Per-velocity constants for a solve; velocity alpha = n_rest + 2 p (+e_p) or
-// n_rest + 2 p + 1 (-e_p).
+// n_rest + 2 p + 1 (-e_p). The velocity components themselves are compile-time
+// constants of the kernels.
 template <typename R>
 struct PairTable {
-    R xi[kMaxPairs][3];             // c * e_p
-    R qq[kMaxPairs][6];             // xi_x^2, xi_y^2, xi_z^2, xi_x xi_y, xi_x xi_z, xi_y xi_z
     R w[kMaxPairs];                 // pair weight
     R wr0[kMaxPairs];               // w * rho0 (F16DEV: w * rho0 / 1024)
     R inv_wr0[kMaxPairs];           // 1 / wr0 (deviation storage)
     double wrd[kMaxPairs];          // w * rho0 in double
-    double shape_p[kMaxPairs];      // w (1 - dt/2 g.xi) for +e_p  (wall slots)
-    double shape_m[kMaxPairs];      // w (1 + dt/2 g.xi) for -e_p
-    int32_t ex[kMaxPairs], ey[kMaxPairs], ez[kMaxPairs];
-    int32_t exm[kMaxPairs];         // ( e_x mod nx) in [0, nx)
-    int32_t exmn[kMaxPairs];        // (-e_x mod nx) in [0, nx)
     R w0, wr00, inv_wr00;           // rest velocity (if any)
-    double wrd0, shape0;
+    double wrd0;
     R c;                            // lattice speed
 };
 
@@ -60,7 +55,7 @@ struct StepScalars {
     double rho0d;
     double invD[4];                 // 1 / D(e) per face (2D: uniform along a face)
     double hgc;                     // dt/2 * g_x * c: wall shape w (1 - hgc e_x)
-    double kA[4][8];                // per face and wall row r: sum of w rho0 over the
+    double kA[4][kMaxWallRows];     // per face and wall row r: sum of w rho0 over the
                                     // velocities leaving through the face from row r
                                     // (deviation storages; 0 otherwise)
     int nx, ny, nz, halo;

@@ -259,7 +259,7 @@ struct L2 {
 
 const Launch *find_launch_2d(int set_id, Storage st) {
     static const Entry entries[] = {
-        LBM_2D(SetD2V17), LBM_2D(SetD2V37), LBM_2D(SetD2V16), LBM_2D(SetD2V33),
+        LBM_2D(SetD2V17), LBM_2D(SetD2V37), LBM_2D(SetD2V16), LBM_2D(SetD2V33), LBM_2D(SetD2V32),
     };
     for (const auto &e : entries)
         if (e.id == set_id && e.s == st) return e.l;

@@ -448,7 +448,7 @@ struct L3 {
         {SET::ID, Storage::F16DEV, &L3<SET, Storage::F16DEV>::table}
 
 const Launch *find_launch_3d(int set_id, Storage st) {
-    static const Entry entries[] = {LBM_3D(SetD3V39), LBM_3D(SetD3V15)};
+    static const Entry entries[] = {LBM_3D(SetD3V39), LBM_3D(SetD3V15), LBM_3D(SetD3V96)};
     for (const auto &e : entries)
         if (e.id == set_id && e.s == st) return e.l;
     return nullptr;

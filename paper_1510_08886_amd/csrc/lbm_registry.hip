@@ -60,6 +60,7 @@ const std::vector<VelSetInfo> &velocity_sets() {
     static const std::vector<VelSetInfo> sets = {
         set_info<SetD2V17>("D2V17"), set_info<SetD2V37>("D2V37"), set_info<SetD2V16>("D2V16"),
         set_info<SetD2V33>("D2V33"), set_info<SetD3V39>("D3V39"), set_info<SetD3V15>("D3V15"),
+        set_info<SetD2V32>("D2V32"), set_info<SetD3V96>("D3V96"),
     };
     return sets;
 }

@@ -17,9 +17,19 @@ def oracle_perm(lib_dvm, o_dvm):
 EXTRA_SETS = {"D3V15": (3, [(0, 0, 0), (2, 0, 0), (1, 1, 1)], 5)}
 
 
+# scattering stencils with compiled kernels, built on both sides from the
+# paper's printed tables (c and weights)
+TABLE_SETS = ("D2V32", "D3V96")
+
+
 def dvm_pair(name):
     from paper_1510_08886_amd import lbm
 
+    if name in TABLE_SETS:
+        from tests.golden.tables import load_dvm_tables
+        m = {t["label"]: t for t in load_dvm_tables()}[name]
+        return (lbm.Dvm(m["D"], m["gens"], m["weights"], m["c"], m["Q"]),
+                odvm.make_dvm(m["D"], m["gens"], m["weights"], m["c"], m["Q"]))
     if name in EXTRA_SETS:
         dim, gens, Q = EXTRA_SETS[name]
         return lbm.Dvm.solve(dim, gens, Q), odvm.solve_dvm(dim, gens, Q)

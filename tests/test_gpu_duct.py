@@ -44,6 +44,8 @@ def load_golden():
     ("D3V39", 3, 64, 6, 6, 3),     # 64-aligned rows, rows next to both faces of each pair
     ("D3V39", 3, 1, 11, 10, 6),    # streamwise-invariant column
     ("D3V15", 3, 33, 5, 8, 5),     # the other compiled 3D set
+    ("D3V96", 3, 9, 7, 8, 2),      # scattering stencil, |e| up to 7: every node a wall node
+    ("D3V96", 4, 64, 15, 14, 2),   # 64-aligned rows, interior nodes
 ])
 def test_f64_duct_random_state_elementwise(name, N, nx, ny, nz, steps):
     nodes = nx * ny * nz
@@ -102,3 +104,14 @@ def test_full_size_duct_against_streamwise_invariant_oracle(storage, tol):
         ux = ob["u"][..., 0]
         assert torch.equal(ux, ux[..., :1].expand_as(ux))   # x columns identical
     s.close()
+
+
+def test_scattering_stencil_duct_low_precision():
+    """D3V96 duct from rest in FP32 and FP16-deviation storage, 150 steps:
+    mass flow against the FP64 oracle."""
+    for storage, tol in (("f32", 1e-5), ("f16dev", 1e-3)):
+        d, g, o = make_pair("D3V96", 3, 2, 16, 16, kn=0.1, storage=storage)
+        g.run(150)
+        o.run(150)
+        got, want = g.observe()["mdot"], o.observe()["mdot"]
+        assert abs(got - want) <= tol * abs(want), (storage, got, want)

@@ -51,6 +51,8 @@ def test_f64_channel_d2v17_full_run():
     ("D2V17", 3, 4, 3, 3),       # ny = largest |e_y|: every row is a wall row
     ("D2V37", 3, 65, 6, 5),      # ny < 2 * halo: rows next to both walls
     ("D2V37", 4, 1, 21, 9),      # streamwise-invariant column
+    ("D2V32", 4, 70, 12, 3),     # scattering stencil, |e| up to 12: every row a wall row
+    ("D2V32", 3, 5, 29, 4),      # nx < |e_x| = 12 (multiple wraps), rows off both walls
 ])
 def test_f64_random_state_elementwise(name, N, nx, ny, steps):
     rho, u = wl.random_state(nx * ny, 2, seed=nx * 131 + ny, amp=2e-2)
@@ -121,3 +123,14 @@ def test_run_to_tol_matches_oracle_steady_state():
     assert r["converged"]
     o.run(r["steps"])
     assert abs(r["mdot"] - o.observe()["mdot"]) <= 1e-12 * abs(r["mdot"])
+
+
+def test_f64_scattering_stencil_channel_run():
+    """Plane Poiseuille flow on the scattering stencil D2V32 (halo 12), Nx = 1,
+    Ny = 36, Kn = 0.2, 3000 steps: mass flow and profile against the oracle."""
+    d, g, o = make_pair("D2V32", 4, 1, 36, kn=0.2, ma=1e-3)
+    g.run(3000)
+    o.run(3000)
+    og, oo = g.observe(), o.observe()
+    assert _rel(og["u"][..., 0].cpu().numpy(), oo["u"][..., 0]) <= 1e-12
+    assert abs(og["mdot"] - oo["mdot"]) <= 1e-12 * abs(oo["mdot"])
