@@ -220,6 +220,46 @@ def duct_block():
     return out
 
 
+def scattering_block():
+    """Scattering stencils (no velocity parallel to the walls): the D2V32
+    channel at 2048 x 512 (halo 12) and the D3V96 duct at 128 x 256 x 256
+    (halo 7), FP32 populations, from the seeded density field / rest. MLUPS and
+    the HBM fraction of the step kernel (algorithmic bytes 2 V 4 per update)."""
+    import torch
+
+    from paper_1510_08886_amd import lbm
+
+    out = {}
+    for key, c in (("d2v32_channel", wl.SCATTER_D2V32), ("d3v96_duct", wl.SCATTER_D3V96)):
+        d = lbm.Dvm.named(c["dvm"])
+        dim = lbm.NAMED_DVMS[c["dvm"]]["dim"]
+        nz = c.get("nz", 1)
+        prob = lbm.Problem(dim=dim, nx=c["nx"], ny=c["ny"], nz=nz, kn=c["kn"], ma=c["ma"],
+                           hermite_order=c["N"], storage="f32")
+        s = lbm.Solver(d, prob, device="cuda:0")
+        nodes = c["nx"] * c["ny"] * nz
+        if dim == 2:
+            s.init(torch.from_numpy(wl.density_field(c["ny"], c["nx"])))
+        else:
+            s.init()
+        s.run(5)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.run(c["steps"])
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        gbs = 2 * d.V * 4 * nodes / (ms * 1e-3 / c["steps"]) / 1e9
+        out[key] = {"V": d.V, "nodes": nodes, "steps": c["steps"],
+                    "mlups": round(nodes * c["steps"] / (ms * 1e-3) / 1e6, 1),
+                    "ms_per_step": ms / c["steps"], "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "mdot": s.mdot()}
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +269,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Kn sweep")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-duct", action="store_true", help="skip the 3D duct runs")
+    ap.add_argument("--no-scatter", action="store_true", help="skip the scattering-stencil runs")
     ap.add_argument("--plain-serve-requests", type=int, default=100,
                     help="prefix of the serving trace run by the one-at-a-time plain baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +351,8 @@ def main():
         out["serving"] = serving_block(args.plain_serve_requests)
     if not args.no_duct:
         out["duct"] = duct_block()
+    if not args.no_scatter:
+        out["scattering"] = scattering_block()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -28,6 +28,9 @@ SERVE = dict(rate=200.0, requests=1000, ny_lo=16, ny_hi=1024, kn_lo=0.01, kn_hi=
 
 # 3D square duct on D3V39: 128 x 256 x 256, walls on y and z, Kn=0.1, N=3.
 DUCT_D3V39 = dict(dvm="D3V39", N=3, nx=128, ny=256, nz=256, kn=0.1, ma=1e-3, steps=500)
+# scattering stencils at the channel / duct sizes above (FP32 populations)
+SCATTER_D2V32 = dict(dvm="D2V32", N=4, nx=2048, ny=512, kn=0.05, ma=1e-3, steps=200)
+SCATTER_D3V96 = dict(dvm="D3V96", N=3, nx=128, ny=256, nz=256, kn=0.1, ma=1e-3, steps=50)
 
 
 def density_field(ny: int, nx: int, seed: int = 1510, amp: float = 1e-3) -> np.ndarray:

@@ -28,6 +28,10 @@ NAMED_DVMS = {
                   Q=9, N=4),
     "D3V39": dict(dim=3, gens=[(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 0, 0), (2, 2, 0), (3, 0, 0)],
                   Q=7, N=3),
+    # scattering stencils (no velocity parallel to a wall)
+    "D2V32": dict(dim=2, gens=[(1, 1), (2, 2), (5, 1), (6, 4), (12, 3)], Q=7, N=4),
+    "D3V96": dict(dim=3, gens=[(1, 1, 1), (3, 3, 3), (3, 1, 1), (4, 4, 4), (7, 1, 1), (6, 6, 1)],
+                  Q=7, N=3),
 }
 
 
