@@ -137,6 +137,28 @@ typedef struct {
 int lbm_dvm_wall_errors(const lbm_dvm_t *dvm, int normal_axis, int cap, int32_t *exps,
                         double *w_exact, double *w_dvm, double *sigma, lbm_wall_report_t *report);
 
+/* ---- channel profile analysis (Section VI) -------------------------------- */
+
+typedef struct {
+    double u_center;  /* u at the channel centre: the middle node (odd ny) or the
+                         cubic through the four middle nodes (even ny) */
+    double u_wall;    /* u on the walls: quadratic through the three nodes next to
+                         each wall, averaged over both walls */
+    double slip;      /* u_s = u_wall / u_center (Eq. defSlip) */
+    double mean;      /* node average of u (the integral of Eq. pf.1) */
+} lbm_profile_stats_t;
+
+/* Slip velocity and Knudsen-layer content of a plane-channel profile u[ny]
+ * (host array; the streamwise velocity at the nodes y_j = (j + 1/2)/ny, e.g.
+ * an x-average of lbm_observe's u). u_ns[ny] receives the parabola with the
+ * same centre value and node-averaged mass flow (Eq. uNS; the continuum factor
+ * 3/(l0/2)^2 is the inverse node average of z^2, z = y - 1/2, so the discrete
+ * mass flow is kept exactly), u_neq[ny] = u - u_ns (Eq. uNEQ). stats, u_ns and
+ * u_neq may be NULL. LBM_E_INVALID unless ny >= 3 (>= 4 when even). Host
+ * only. */
+int lbm_profile_analysis(const double *u, int ny, lbm_profile_stats_t *stats, double *u_ns,
+                         double *u_neq);
+
 /* ---- solver --------------------------------------------------------------- */
 
 /* Derived scalars for a problem (pure host). */

@@ -15,7 +15,8 @@ LIB = PKG / "liblbmdvm.so"
 BUILD_DIR = ROOT / "_build"
 
 SOURCES = ["lbm_kernels.hip", "lbm_kernels3d.hip", "lbm_batch.hip", "lbm_registry.hip", "lbm_api.cpp",
-           "lbm_dvm.cpp", "lbm_wall.cpp"]
+           "lbm_dvm.cpp", "lbm_wall.cpp",
+           "lbm_profile.cpp"]
 
 # gfx950 only; packed FP32 instructions are switched off for all device code.
 HIPCC_FLAGS = [

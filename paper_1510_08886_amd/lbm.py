@@ -65,6 +65,11 @@ class WallReportC(ctypes.Structure):
                 ("lambda_index", ctypes.c_uint64), ("sigma_sigma", ctypes.c_double)]
 
 
+class ProfileStatsC(ctypes.Structure):
+    _fields_ = [("u_center", ctypes.c_double), ("u_wall", ctypes.c_double),
+                ("slip", ctypes.c_double), ("mean", ctypes.c_double)]
+
+
 class BatchStatsC(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int), ("queued", ctypes.c_int), ("done", ctypes.c_int),
                 ("threads", ctypes.c_int), ("quantum", ctypes.c_int), ("launches", ctypes.c_int64),
@@ -88,6 +93,7 @@ SIGNATURES = {
     "lbm_dvm_create": ([_I, _I, _I32P, _DP, _D, _I, ctypes.POINTER(_P)], _I),
     "lbm_dvm_destroy": ([_P], _I),
     "lbm_dvm_info": ([_P, _IP, _I32P, _DP, _DP], _I),
+    "lbm_profile_analysis": ([_DP, _I, ctypes.POINTER(ProfileStatsC), _DP, _DP], _I),
     "lbm_dvm_wall_errors": ([_P, _I, _I, _I32P, _DP, _DP, _DP, ctypes.POINTER(WallReportC)], _I),
     "lbm_params": ([_P, ctypes.POINTER(ProblemC), ctypes.POINTER(ParamsC)], _I),
     "lbm_state_bytes": ([_P, ctypes.POINTER(ProblemC), _SZP, _SZP], _I),
@@ -143,6 +149,20 @@ def _i32(a):
 def _f64(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(_DP)
+
+
+def profile_analysis(u) -> dict:
+    """Slip velocity and Knudsen-layer split of a channel profile u[ny] (host
+    values, e.g. the x-average of Solver.observe()["u"][..., 0])."""
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))
+    ny = len(u)
+    st = ProfileStatsC()
+    ns, neq = np.zeros(ny), np.zeros(ny)
+    check(lib().lbm_profile_analysis(u.ctypes.data_as(_DP), ny, ctypes.byref(st),
+                                     ns.ctypes.data_as(_DP), neq.ctypes.data_as(_DP)),
+          "lbm_profile_analysis")
+    return dict(u_center=st.u_center, u_wall=st.u_wall, slip=st.slip, mean=st.mean, u_ns=ns,
+                u_neq=neq)
 
 
 class Dvm:

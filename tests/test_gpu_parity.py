@@ -134,3 +134,18 @@ def test_f64_scattering_stencil_channel_run():
     og, oo = g.observe(), o.observe()
     assert _rel(og["u"][..., 0].cpu().numpy(), oo["u"][..., 0]) <= 1e-12
     assert abs(og["mdot"] - oo["mdot"]) <= 1e-12 * abs(oo["mdot"])
+
+
+def test_slip_and_knudsen_layer_of_gpu_profile():
+    """Slip velocity and Knudsen-layer split (lbm_profile_analysis) of a GPU
+    channel profile against the oracle's analysis of the oracle's profile."""
+    from oracle import profile
+    from paper_1510_08886_amd import lbm
+    d, g, o = make_pair("D2V37", 4, 1, 40, kn=0.2, ma=1e-3)
+    g.run(4000)
+    o.run(4000)
+    ug = g.observe()["u"][..., 0].mean(dim=-1).cpu().numpy()
+    uo = o.observe()["u"][..., 0].mean(axis=-1)
+    rg, ro = lbm.profile_analysis(ug), profile.analyse(uo)
+    assert abs(rg["slip"] - ro["slip"]) <= 1e-12 * abs(ro["slip"])
+    assert np.max(np.abs(rg["u_neq"] - ro["u_neq"])) <= 1e-12 * np.max(np.abs(uo))
