@@ -237,6 +237,8 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
     s->aligned_rows = (p.nx % 64) == 0;
+    s->stream_stores = 2.0 * (double)d.V * (double)s->plane * (double)storage_bytes(p.storage) >
+                       (double)(1u << 30);
 }
 
 // 1 / D(e) of a duct's wall elements, [face][position along the face]. A

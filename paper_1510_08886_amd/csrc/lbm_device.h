@@ -117,6 +117,19 @@ __device__ __forceinline__ double stored_part(typename St<S>::T v, typename St<S
         return (double)v;
 }
 
+// Population store of a time step. STREAM selects the non-temporal
+// (streaming) hint: the value is not read again in this launch. Measured on
+// MI355X: it speeds up the 128x256x256 D3V39 duct (2.6 GB of populations) by
+// 4% (FP32) and 8% (FP16), and slows the 2048x512 D2V37 channel (310 MB, close
+// to the 256 MB last-level cache that can serve the next step's reads) by 5%.
+template <bool STREAM, typename T>
+__device__ __forceinline__ void store_pop(T *p, T v) {
+    if constexpr (STREAM)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // per-node random word for stochastic rounding (n = solve-local node index)
 __device__ __forceinline__ uint32_t node_key(uint32_t n, uint32_t step) {
     return pcg_hash(n ^ pcg_hash(step));

@@ -61,6 +61,7 @@ struct StepScalars {
     int nx, ny, nz, halo;
     int64_t plane;                  // nodes rounded up to whole 64-node blocks
     int aligned_rows;               // nx is a multiple of 64: a row starts a block
+    int stream_stores;              // populations (both copies) above 1 GiB: streaming stores
     int64_t nodes;
 };
 

@@ -40,7 +40,7 @@ namespace lbm {
 //   complete2d decodes them to deviations and replaces the values whose source
 //              lies outside by the diffuse-wall populations.
 // ---------------------------------------------------------------------------
-template <class SET, Storage S>
+template <class SET, Storage S, bool ALIGNED>
 __device__ __forceinline__ void issue2d(const typename St<S>::T *__restrict__ src,
                                         const StepScalars<typename St<S>::R> &s, int i, int j,
                                         typename St<S>::T (&raw)[SET::V]) {
@@ -55,7 +55,7 @@ __device__ __forceinline__ void issue2d(const typename St<S>::T *__restrict__ sr
 #pragma unroll
     for (int k = -HN; k <= HN; ++k) rows[k + HN] = min(max(j - k, 0), ny - 1);
     if constexpr (NR) raw[0] = src[aos_base<V>((uint32_t)j * nx + i)];
-    if (s.aligned_rows) {
+    if constexpr (ALIGNED) {
         // a row is a whole number of blocks: index = row base + column part
         const uint32_t rowstride = (uint32_t)nx * V;
         uint32_t cp[2 * H + 1];
@@ -87,12 +87,12 @@ __device__ __forceinline__ void gather2d(const typename St<S>::T *__restrict__ s
                                          const StepScalars<typename St<S>::R> &s, int i, int j,
                                          typename St<S>::R (&d)[SET::V]) {
     typename St<S>::T raw[SET::V];
-    issue2d<SET, S>(src, s, i, j, raw);
+    issue2d<SET, S, false>(src, s, i, j, raw);
     complete2d<SET, S>(raw, a_cur, t, s, i, j, d);
 }
 
 // store d[] and, on wall rows, the FP64 partial of what leaves next step
-template <class SET, Storage S, bool SRND>
+template <class SET, Storage S, bool SRND, bool STREAM = false>
 __device__ __forceinline__ void scatter2d(typename St<S>::T *__restrict__ dst,
                                           double *__restrict__ a_next,
                                           const PairTable<typename St<S>::R> &t,
@@ -104,19 +104,23 @@ __device__ __forceinline__ void scatter2d(typename St<S>::T *__restrict__ dst,
     encode_all<SET, S, SRND>(d, t, n, step, v);
     T *out = dst + aos_base<SET::V>(n);
 #pragma unroll
-    for (int a = 0; a < SET::V; ++a) out[64 * a] = v[a];
+    for (int a = 0; a < SET::V; ++a) store_pop<STREAM>(out + 64 * a, v[a]);
     wall_partials2d<SET, S>(v, t, s, i, j, a_next);
 }
 
 // One block of 256 threads per tile of 256 consecutive nodes. Each thread
 // issues the pull loads of all its velocities before it decodes any of them,
 // so a wavefront has its whole gather in flight at once; the wall slots are
-// patched after the loads. (Measured on MI355X: this beats a persistent grid
-// with a two-stage load pipeline, whose second register buffer halves the
-// occupancy, and 128- or 512-node tiles.)
-template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t,
-                                                StepScalars<typename St<S>::R> s, uint32_t step) {
+// patched after the loads. ALIGNED (nx a multiple of 64) is compiled apart so
+// the common case carries no registers of the general index path. Measured on
+// MI355X against: a persistent grid with a two-stage register load pipeline
+// (occupancy 2), a persistent grid streaming the next tile's gather into LDS
+// with global_load_lds (LDS-limited to 8 waves per CU), 64-, 128- and 512-node
+// tiles, and register caps for 6, 7 or 8 waves per SIMD.
+template <class SET, Storage S, bool ALIGNED, bool STREAM>
+__global__ __launch_bounds__(256)
+void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
+              uint32_t step) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
     const uint32_t n = blockIdx.x * 256u + threadIdx.x;
@@ -124,11 +128,11 @@ __global__ __launch_bounds__(256) void k_step2d(StepBuffers b, PairTable<typenam
     const int j = (int)(n / (uint32_t)s.nx);
     const int i = (int)(n - (uint32_t)j * s.nx);
     T raw[SET::V];
-    issue2d<SET, S>((const T *)b.src, s, i, j, raw);
+    issue2d<SET, S, ALIGNED>((const T *)b.src, s, i, j, raw);
     R d[SET::V];
     complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
     relax2d<SET, R>(d, t, s, t.c);
-    scatter2d<SET, S, true>((T *)b.dst, b.a_next, t, s, i, j, d, step);
+    scatter2d<SET, S, true, STREAM>((T *)b.dst, b.a_next, t, s, i, j, d, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -211,8 +215,13 @@ struct L2 {
                     uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        hipLaunchKernelGGL((k_step2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, b, t,
-                           s, stp);
+        const dim3 g(blocks_for(s.nodes)), bl(256);
+        if (s.aligned_rows && s.stream_stores)
+            hipLaunchKernelGGL((k_step2d<SET, S, true, true>), g, bl, 0, st, b, t, s, stp);
+        else if (s.aligned_rows)
+            hipLaunchKernelGGL((k_step2d<SET, S, true, false>), g, bl, 0, st, b, t, s, stp);
+        else
+            hipLaunchKernelGGL((k_step2d<SET, S, false, false>), g, bl, 0, st, b, t, s, stp);
         return hip_ok(hipGetLastError(), "step kernel launch");
     }
     static int init(void *dst, double *a_out, const double *rho, const double *u, const void *tab,

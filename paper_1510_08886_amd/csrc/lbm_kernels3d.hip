@@ -70,8 +70,12 @@ __device__ __forceinline__ Moments3D<R> moments3d(const R (&d)[SET::V], const St
     return m;
 }
 
-// equilibrium (scalar Hermite recurrence) + force of Eq. nm.4 (g along x) +
-// BGK relaxation of the modified populations, on deviations d = fbar - w rho0
+// Equilibrium + force (Eq. nm.4, g along x) + BGK relaxation per velocity pair,
+// with the Hermite sums as polynomials in the integer velocity e whose
+// coefficients are formed once per node (as in the 2D channel):
+//   even(e) = C0 + ue^2 (C2 + C4 ue^2) + e_x T ue
+//   odd(e)  = ue (R1 + rc3 ue^2) + e.L
+//             + e_x (e_x^2 Kxx + e_y^2 Kyy + e_z^2 Kzz + e_x e_y Kxy + e_x e_z Kxz + e_y e_z Kyz)
 template <class SET, typename R>
 __device__ __forceinline__ void relax3d(R (&d)[SET::V], const PairTable<R> &t,
                                         const StepScalars<R> &s, R c) {
@@ -91,44 +95,40 @@ __device__ __forceinline__ void relax3d(R (&d)[SET::V], const PairTable<R> &t,
     const R a2yz = (m.syz + hr * uy * uz) * i1h;
     const R tra2 = a2xx + a2yy + a2zz;
     const R c2 = c * c;
-    const R qxx = a2xx * c2, qyy = a2yy * c2, qzz = a2zz * c2;
-    const R qxy = R(2) * a2xy * c2, qxz = R(2) * a2xz * c2, qyz = R(2) * a2yz * c2;
     const R gxc = gx * c;
-    const R hxc = a2xx * gxc, hyc = a2xy * gxc, hzc = a2xz * gxc;   // (a2 g) . xi
     const R uxc = ux * c, uyc = uy * c, uzc = uz * c;
     const R u2 = ux * ux + uy * uy + uz * uz;
-    const R u2_3 = R(3) * u2;
-    const R ug = ux * gx;
     const R tr = s.tau * rho;
-    const R trgxc = tr * gxc;
-    const R half_tau = R(0.5) * s.tau;
     const R rc2 = rho * s.cn[2], rc3 = rho * s.cn[3], rc4 = rho * s.cn[4];
     const R om = s.omega;
-    const R even0 = drho - tr * ug;
-    if constexpr (NR) {
-        const R even = fma(rc2, -u2, fma(rc4, u2_3 * u2, even0));
-        d[0] = fma(om, fma(t.w0, even, -d[0]), d[0]);
-    }
+    const R C0 = fma(R(3) * rc4 * u2, u2, fma(-rc2, u2, drho - tr * ux * gx));
+    const R C2 = fma(R(-6) * rc4, u2, rc2);
+    const R C4 = rc4;
+    const R T = tr * gxc;
+    const R R1 = fma(R(-3) * rc3, u2, rho);
+    const R hgt = R(0.5) * s.tau * gxc;
+    const R Lx = fma(gxc, fma(R(-0.5) * s.tau, tra2, tr), -s.tau * a2xx * gxc);
+    const R Ly = -s.tau * a2xy * gxc;
+    const R Lz = -s.tau * a2xz * gxc;
+    const R hc2 = hgt * c2;
+    const R Kxx = hc2 * a2xx, Kyy = hc2 * a2yy, Kzz = hc2 * a2zz;
+    const R Kxy = R(2) * hc2 * a2xy, Kxz = R(2) * hc2 * a2xz, Kyz = R(2) * hc2 * a2yz;
+    if constexpr (NR) d[0] = fma(om, fma(t.w0, C0, -d[0]), d[0]);
     for_pairs<SET::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
         const R ue = lin3<ex, ey, ez>(uxc, uyc, uzc);
         const R ue2 = ue * ue;
-        const R P2 = ue2 - u2;
-        const R P3 = ue * (ue2 - u2_3);
-        const R P4 = fma(ue, P3, -u2_3 * P2);
-        R even = fma(rc2, P2, fma(rc4, P4, even0));
-        R odd = fma(rc3, P3, rho * ue);
-        if constexpr (ex != 0) {
-            even = fma(mulk<ex>(trgxc), ue, even);
-            // a2 : xi xi (the off-diagonal terms carry their factor 2)
-            R q = lin3<ex * ex, ey * ey, ez * ez>(qxx, qyy, qzz);
-            q = addk<ex * ey>(q, qxy);
-            q = addk<ex * ez>(q, qxz);
-            q = addk<ey * ez>(q, qyz);
-            odd = fma(mulk<ex>(gxc), fma(half_tau, q - tra2, tr), odd);
-        }
-        if constexpr (ex != 0 || ey != 0 || ez != 0) odd = fma(-s.tau, lin3<ex, ey, ez>(hxc, hyc, hzc), odd);
+        R even = fma(fma(C4, ue2, C2), ue2, C0);
+        if constexpr (ex != 0) even = fma(mulk<ex>(T), ue, even);
+        R f = lin3<ex, ey, ez>(Lx, Ly, Lz);
+        f = addk<ex * ex * ex>(f, Kxx);
+        f = addk<ex * ey * ey>(f, Kyy);
+        f = addk<ex * ez * ez>(f, Kzz);
+        f = addk<ex * ex * ey>(f, Kxy);
+        f = addk<ex * ex * ez>(f, Kxz);
+        f = addk<ex * ey * ez>(f, Kyz);
+        const R odd = fma(ue, fma(rc3, ue2, R1), f);
         const R w = t.w[p];
         R &dp = d[NR + 2 * p];
         R &dm = d[NR + 2 * p + 1];
@@ -157,7 +157,7 @@ __device__ __forceinline__ int first_face(int j, int k, int vy, int vz, bool oy,
 // ---------------------------------------------------------------------------
 // gather
 // ---------------------------------------------------------------------------
-template <class SET, Storage S>
+template <class SET, Storage S, bool ALIGNED>
 __device__ __forceinline__ void issue3d(const typename St<S>::T *__restrict__ src,
                                         const StepScalars<typename St<S>::R> &s, int i, int j,
                                         int k, typename St<S>::T (&raw)[SET::V]) {
@@ -173,7 +173,7 @@ __device__ __forceinline__ void issue3d(const typename St<S>::T *__restrict__ sr
         rz[q + HN] = min(max(k - q, 0), nz - 1);
     }
     if constexpr (NR) raw[0] = src[aos_base<V>(((uint32_t)k * ny + j) * nx + i)];
-    if (s.aligned_rows) {
+    if constexpr (ALIGNED) {
         const uint32_t rowstride = (uint32_t)nx * V;
         uint32_t cp[2 * H + 1];
 #pragma unroll
@@ -285,7 +285,7 @@ __device__ __forceinline__ void wall_partials3d(const typename St<S>::T (&v)[SET
     if (zhi) a_next[kZHi * fs + (int64_t)(nz - 1 - k) * epz + (int64_t)j * nx + i] = acc[kZHi];
 }
 
-template <class SET, Storage S, bool SRND>
+template <class SET, Storage S, bool SRND, bool STREAM = false>
 __device__ __forceinline__ void scatter3d(typename St<S>::T *__restrict__ dst,
                                           double *__restrict__ a_next,
                                           const PairTable<typename St<S>::R> &t,
@@ -298,7 +298,7 @@ __device__ __forceinline__ void scatter3d(typename St<S>::T *__restrict__ dst,
     encode_all<SET, S, SRND>(d, t, n, step, v);
     T *out = dst + aos_base<SET::V>(n);
 #pragma unroll
-    for (int a = 0; a < SET::V; ++a) out[64 * a] = v[a];
+    for (int a = 0; a < SET::V; ++a) store_pop<STREAM>(out + 64 * a, v[a]);
     wall_partials3d<SET, S>(v, t, s, i, j, k, a_next);
 }
 
@@ -309,9 +309,11 @@ __device__ __forceinline__ void node_ijk(uint32_t n, int nx, int ny, int &i, int
     j = (int)(row - (uint32_t)k * ny);
 }
 
-template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t,
-                                                StepScalars<typename St<S>::R> s, uint32_t step) {
+// ALIGNED (nx a multiple of 64) is compiled apart.
+template <class SET, Storage S, bool ALIGNED, bool STREAM>
+__global__ __launch_bounds__(256)
+void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
+              uint32_t step) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
     const uint32_t n = blockIdx.x * 256u + threadIdx.x;
@@ -319,11 +321,11 @@ __global__ __launch_bounds__(256) void k_step3d(StepBuffers b, PairTable<typenam
     int i, j, k;
     node_ijk(n, s.nx, s.ny, i, j, k);
     T raw[SET::V];
-    issue3d<SET, S>((const T *)b.src, s, i, j, k, raw);
+    issue3d<SET, S, ALIGNED>((const T *)b.src, s, i, j, k, raw);
     R d[SET::V];
     complete3d<SET, S>(raw, b.a_cur, b.invd, t, s, i, j, k, d);
     relax3d<SET, R>(d, t, s, t.c);
-    scatter3d<SET, S, true>((T *)b.dst, b.a_next, t, s, i, j, k, d, step);
+    scatter3d<SET, S, true, STREAM>((T *)b.dst, b.a_next, t, s, i, j, k, d, step);
 }
 
 template <class SET, Storage S>
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(256) void k_observe3d(const void *src, const double
         int i, j, k;
         node_ijk(n, s.nx, s.ny, i, j, k);
         T raw[SET::V];
-        issue3d<SET, S>((const T *)src, s, i, j, k, raw);
+        issue3d<SET, S, false>((const T *)src, s, i, j, k, raw);
         R d[SET::V];
         complete3d<SET, S>(raw, a_cur, invd, t, s, i, j, k, d);
         const auto m = moments3d<SET, R>(d, s, t.c);
@@ -401,8 +403,13 @@ struct L3 {
                     uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        hipLaunchKernelGGL((k_step3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, b, t,
-                           s, stp);
+        const dim3 g(blocks_for(s.nodes)), bl(256);
+        if (s.aligned_rows && s.stream_stores)
+            hipLaunchKernelGGL((k_step3d<SET, S, true, true>), g, bl, 0, st, b, t, s, stp);
+        else if (s.aligned_rows)
+            hipLaunchKernelGGL((k_step3d<SET, S, true, false>), g, bl, 0, st, b, t, s, stp);
+        else
+            hipLaunchKernelGGL((k_step3d<SET, S, false, false>), g, bl, 0, st, b, t, s, stp);
         return hip_ok(hipGetLastError(), "3D step kernel launch");
     }
     static int init(void *dst, double *a_out, const double *rho, const double *u, const void *tab,

@@ -47,6 +47,17 @@ __device__ __forceinline__ Moments2D<R> moments2d(const R (&d)[SET::V], const St
     return m;
 }
 
+// Equilibrium + force + BGK relaxation per velocity pair (e, -e), with the
+// Hermite sums regrouped as polynomials in the integer velocity e, whose
+// coefficients are formed once per node (ue = u.xi, u2 = |u|^2, xi = c e):
+//   f^(0)/w  = drho + rho [1 + ue + (ue^2 - u2)/2 + (ue^3 - 3 u2 ue)/6
+//                          + (ue^4 - 6 u2 ue^2 + 3 u2^2)/24]   (terms up to N)
+//   tau F/w  = tau rho [(g.xi) + (g.xi)(u.xi) - g.u]
+//              + tau/2 (g.xi)(a2 : xi xi - tr a2) - tau (a2 g).xi  (Eq. nm.4)
+// so that, with g along x,
+//   even(e) = C0 + ue^2 (C2 + C4 ue^2) + e_x T ue
+//   odd(e)  = ue (R1 + rc3 ue^2) + e.L + e_x (e_x^2 Kxx + e_y^2 Kyy + e_x e_y Kxy)
+// and fbar* = fbar + omega (w (even +- odd) - fbar) (Eq. nm.8) on deviations.
 template <class SET, typename R>
 __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
                                         const StepScalars<R> &s, R c) {
@@ -62,43 +73,36 @@ __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
     const R a2xy = (m.sxy + hr * ux * uy + htr * gx * uy) * s.inv1h;
     const R tra2 = a2xx + a2yy;
     const R c2 = c * c;
-    const R qxx = a2xx * c2, qyy = a2yy * c2, qxy = a2xy * c2;   // a2 : xi xi
-    const R hxc = a2xx * gx * c, hyc = a2xy * gx * c;              // (a2 g) . xi
-    const R uxc = ux * c, uyc = uy * c;
     const R gxc = gx * c;
+    const R uxc = ux * c, uyc = uy * c;
     const R u2 = ux * ux + uy * uy;
-    const R u2_3 = R(3) * u2;
-    const R ug = ux * gx;
     const R tr = s.tau * rho;
-    const R trgxc = tr * gxc;
-    const R half_tau = R(0.5) * s.tau;
     const R rc2 = rho * s.cn[2], rc3 = rho * s.cn[3], rc4 = rho * s.cn[4];
     const R om = s.omega;
-    const R even0 = drho - tr * ug;   // part of the even term shared by all velocities
-    if constexpr (NR) {
-        // rest velocity: P2 = -u2, P4 = 3 u2^2, no odd part
-        const R even = fma(rc2, -u2, fma(rc4, u2_3 * u2, even0));
-        d[0] = fma(om, fma(t.w0, even, -d[0]), d[0]);
-    }
+    // even part: C0 is also the rest velocity's value (ue = 0)
+    const R C0 = fma(R(3) * rc4 * u2, u2, fma(-rc2, u2, drho - tr * ux * gx));
+    const R C2 = fma(R(-6) * rc4, u2, rc2);
+    const R C4 = rc4;
+    const R T = tr * gxc;
+    // odd part
+    const R R1 = fma(R(-3) * rc3, u2, rho);
+    const R hgt = R(0.5) * s.tau * gxc;
+    const R Lx = fma(gxc, fma(R(-0.5) * s.tau, tra2, tr), -s.tau * a2xx * gxc);
+    const R Ly = -s.tau * a2xy * gxc;
+    const R Kxx = hgt * a2xx * c2, Kyy = hgt * a2yy * c2, Kxy = R(2) * hgt * a2xy * c2;
+    if constexpr (NR) d[0] = fma(om, fma(t.w0, C0, -d[0]), d[0]);
     for_pairs<SET::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int ex = SET::EX[p], ey = SET::EY[p];
         const R ue = lin2<ex, ey>(uxc, uyc);
         const R ue2 = ue * ue;
-        const R P2 = ue2 - u2;
-        const R P3 = ue * (ue2 - u2_3);
-        const R P4 = fma(ue, P3, -u2_3 * P2);
-        // even: drho + rho (P2/2 + P4/24) + tau rho ((g.xi)(u.xi) - u.g)
-        R even = fma(rc2, P2, fma(rc4, P4, even0));
-        R odd = fma(rc3, P3, rho * ue);
-        if constexpr (ex != 0) {
-            even = fma(mulk<ex>(trgxc), ue, even);
-            // tau F, odd part: (g.xi) [tau rho + tau/2 (a2 : xi xi - tr a2)]
-            const R q = lin3<ex * ex, ey * ey, 2 * ex * ey>(qxx, qyy, qxy);
-            odd = fma(mulk<ex>(gxc), fma(half_tau, q - tra2, tr), odd);
-        }
-        // - tau (a2 g) . xi
-        if constexpr (ex != 0 || ey != 0) odd = fma(-s.tau, lin2<ex, ey>(hxc, hyc), odd);
+        R even = fma(fma(C4, ue2, C2), ue2, C0);
+        if constexpr (ex != 0) even = fma(mulk<ex>(T), ue, even);
+        R f = lin2<ex, ey>(Lx, Ly);
+        f = addk<ex * ex * ex>(f, Kxx);
+        f = addk<ex * ey * ey>(f, Kyy);
+        f = addk<ex * ex * ey>(f, Kxy);
+        const R odd = fma(ue, fma(rc3, ue2, R1), f);
         const R w = t.w[p];
         R &dp = d[NR + 2 * p];
         R &dm = d[NR + 2 * p + 1];
