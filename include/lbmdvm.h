@@ -164,14 +164,18 @@ int lbm_profile_analysis(const double *u, int ny, lbm_profile_stats_t *stats, do
 /* Derived scalars for a problem (pure host). */
 int lbm_params(const lbm_dvm_t *dvm, const lbm_problem_t *prob, lbm_params_t *out);
 
-/* Bytes the caller must provide: each of the two population buffers
- * (*pop_bytes) and the scratch buffer (*scratch_bytes). */
+/* Bytes the caller must provide: the population buffer (*pop_bytes: one copy of
+ * the populations up to 512 MiB per copy, two copies above) and the scratch
+ * buffer (*scratch_bytes). */
 int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, size_t *pop_bytes,
                     size_t *scratch_bytes);
 
-/* Create a solver over caller device buffers pop_a, pop_b (ping-pong
- * populations, each >= pop_bytes) and scratch (>= scratch_bytes), all aligned to
- * 256 bytes, on the HIP stream `stream` (hipStream_t; NULL = default stream).
+/* Create a solver over caller device buffers pop_a (populations, >= pop_bytes)
+ * and scratch (>= scratch_bytes), both aligned to 256 bytes, on the HIP stream
+ * `stream` (hipStream_t; NULL = default stream). Up to 512 MiB of populations
+ * the update runs in place in one array (each step reads and writes the same
+ * locations per node, alternating two layouts); above that pop_a holds two
+ * copies, stepped ping-pong. pop_b is not used and may be NULL.
  * Validation (LBM_E_INVALID): ny (and nz in 3D) >= the largest |e_n|;
  * 2 <= N <= (Q+1)/2; kn > 0; g.n = 0; sizes positive. accommodation != 1 gives
  * LBM_E_UNSUPPORTED, as does a velocity count without a compiled kernel. */

@@ -19,8 +19,12 @@ SOURCES = ["lbm_kernels.hip", "lbm_kernels3d.hip", "lbm_batch.hip", "lbm_registr
            "lbm_profile.cpp"]
 
 # gfx950 only; packed FP32 instructions are switched off for all device code.
+# Multiply-adds are fused only within a source expression (-ffp-contract=on),
+# never across statements by the backend, so that the same node arithmetic
+# inlined into different kernels (the two in-place step kinds, the batched
+# kernel) rounds identically: results are bitwise independent of the kernel.
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

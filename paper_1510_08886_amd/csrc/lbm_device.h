@@ -1,6 +1,6 @@
 // Device-side helpers shared by the 2D channel, 3D duct and batched kernels:
 // storage encodings, stochastic rounding, compile-time pair loops, the Hermite
-// equilibrium for initial states, FP64 block sums and the export kernel.
+// equilibrium for initial states and FP64 block sums.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -292,24 +292,27 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *partial) 
     }
 }
 
-// canonical FP64 export [alpha][node]
-template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_export(const void *src, double *out,
-                                                PairTable<typename St<S>::R> t,
-                                                StepScalars<typename St<S>::R> s) {
-    using T = typename St<S>::T;
+// ---------------------------------------------------------------------------
+// node-local accesses of the in-place population array (PopLayout), shared by
+// the 2D and 3D kernels
+// ---------------------------------------------------------------------------
+// STREAMED -> pre-collision values: slot alpha of the node itself
+template <class SET, typename T>
+__device__ __forceinline__ void read_local(const T *A, uint32_t own, T (&raw)[SET::V]) {
+#pragma unroll
+    for (int a = 0; a < SET::V; ++a) raw[a] = A[own + 64 * a];
+}
+
+// post-collision values -> the node's own slots: kLocal (SWAP, velocity alpha
+// in the slot of -alpha) or kDirect (slot alpha)
+template <class SET, bool SWAP, bool STREAM, typename T>
+__device__ __forceinline__ void write_own(T *A, uint32_t own, const T (&v)[SET::V]) {
     constexpr int NR = SET::NR;
-    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= (uint32_t)s.nodes) return;
-    const uint32_t nodes = (uint32_t)s.nodes;
-    const T *f = (const T *)src + aos_base<SET::V>(n);
-    if constexpr (NR) out[n] = stored_value<S>(f[0], t.wrd0);
+    if constexpr (NR) store_pop<STREAM>(A + own, v[0]);
     for_pairs<SET::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        for (int m = 0; m < 2; ++m) {
-            const uint32_t a = NR + 2 * p + m;
-            out[a * nodes + n] = stored_value<S>(f[64 * a], t.wrd[p]);
-        }
+        store_pop<STREAM>(A + own + 64 * (SWAP ? NR + 2 * p + 1 : NR + 2 * p), v[NR + 2 * p]);
+        store_pop<STREAM>(A + own + 64 * (SWAP ? NR + 2 * p : NR + 2 * p + 1), v[NR + 2 * p + 1]);
     });
 }
 

@@ -67,25 +67,43 @@ struct StepScalars {
 
 enum class Storage : int { F64 = LBM_F64, F32 = LBM_F32, F16DEV = LBM_F16DEV, F32RAW = LBM_F32RAW };
 
+// Layouts of the population array of a solve.
+//   kDirect   : node x holds its own post-collision populations, velocity alpha
+//               in slot alpha (two arrays, ping-pong pull steps);
+// and, for one array updated in place (the AA pattern):
+//   kLocal    : node x holds its own post-collision populations, velocity alpha
+//               in the slot of -alpha (after init, import and kStreamed steps);
+//   kStreamed : slot alpha of node y holds the post-collision population that
+//               streams into y along alpha from y - e_alpha; a population that
+//               leaves through a wall stays at its node, in the slot of -alpha
+//               (after kLocal steps).
+// A step on a kLocal array gathers from and writes to the neighbours; a step on
+// a kStreamed array reads and writes the node itself. Both read and write the
+// same set of locations per node, so nodes never race.
+enum PopLayout : int { kLocal = 0, kStreamed = 1, kDirect = 2 };
+
 // Buffers of one solve (device pointers).
 struct StepBuffers {
-    const void *src;
-    void *dst;
-    const double *a_cur;            // wall-flux partials of src  [face][halo][elements]
-    double *a_next;                 // wall-flux partials of dst
+    void *pop;                      // the population array (ping-pong: the source)
+    void *pop_out;                  // ping-pong: the destination; in place: unused
+    int layout;                     // PopLayout of pop before the step
+    const double *a_cur;            // wall-flux partials of the current state [face][halo][elements]
+    double *a_next;                 // wall-flux partials written by the step
     const double *invd;             // 3D: 1 / D(e) per face and position along it
 };
 
-// Launchers (instantiated in the .hip translation unit).
+// Launchers (instantiated in the .hip translation units).
 struct Launch {
     int (*step)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, uint32_t step);
-    int (*init)(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
-                const void *sc, hipStream_t, uint32_t step);
-    int (*observe)(const void *src, const double *a_cur, const double *invd, double *rho, double *u,
-                   double *partial, const void *tab, const void *sc, hipStream_t);
-    int (*exportp)(const void *src, double *out, const void *tab, const void *sc, hipStream_t);
-    int (*importp)(void *dst, double *a_out, const double *in, const void *tab, const void *sc,
-                   hipStream_t, uint32_t step);
+    int (*init)(void *pop, int layout, double *a_out, const double *rho, const double *u,
+                const void *tab, const void *sc, hipStream_t, uint32_t step);
+    int (*observe)(const void *pop, int layout, const double *a_cur, const double *invd,
+                   double *rho, double *u, double *partial, const void *tab, const void *sc,
+                   hipStream_t);
+    int (*exportp)(const void *pop, int layout, double *out, const void *tab, const void *sc,
+                   hipStream_t);
+    int (*importp)(void *pop, int layout, double *a_out, const double *in, const void *tab,
+                   const void *sc, hipStream_t, uint32_t step);
 };
 
 // Velocity sets with compiled kernels (library velocity order).

@@ -4,9 +4,10 @@
 //
 // Layout in HBM: blocks of 64 consecutive nodes (node n = y * nx + x) with all
 // populations of a block together, one contiguous 64-entry run per velocity
-// (aos_base). A wavefront covers one block: every store is a whole aligned run
-// and every pull load of velocity alpha is one run shifted by the velocity,
-// spanning at most two blocks of the source row.
+// slot (aos_base). A wavefront covers one block; a neighbour access of
+// velocity alpha is one run shifted by the velocity, spanning at most two
+// blocks of the neighbouring row. One array per solve, updated in place
+// (PopLayout).
 //
 // Kernels are specialised per velocity set (lbm_sets.h): integer velocity
 // components are compile-time constants, so moments are integer-weighted sums,
@@ -33,91 +34,105 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// 2D gather: pull-stream from src with wall slots, in two phases so that the
-// loads of one node can be in flight while another node is collided:
-//   issue2d    loads the raw stored values of the pull sources; rows outside
-//              the channel are clamped so every address is valid;
-//   complete2d decodes them to deviations and replaces the values whose source
-//              lies outside by the diffuse-wall populations.
+// One population array per solve (the AA pattern; two layouts, see
+// PopLayout). A step reads and writes the same set of locations per node, so
+// nodes never race, and the update runs in place: half the memory of a
+// ping-pong pair, and for arrays that fit the 256 MB last-level cache the next
+// step is largely served from it.
+//
+// Neighbour addressing of node (i, j): element index of slot 0 of node
+// (j - dy, i - dx), |dy| <= HN, |dx| <= H, rows clamped into the channel (so
+// every address is valid), columns periodic. ALIGNED (nx % 64 == 0): a row is
+// a whole number of 64-node blocks, so the index is row part + column part.
 // ---------------------------------------------------------------------------
-template <class SET, Storage S, bool ALIGNED>
-__device__ __forceinline__ void issue2d(const typename St<S>::T *__restrict__ src,
-                                        const StepScalars<typename St<S>::R> &s, int i, int j,
-                                        typename St<S>::T (&raw)[SET::V]) {
-    constexpr int NR = SET::NR, H = SET::H, HN = SET::HN, V = SET::V;
-    const int nx = s.nx, ny = s.ny;
-    // column offsets (i - k) mod nx for k in [-H, H]
-    uint32_t xo[2 * H + 1];
-#pragma unroll
-    for (int k = -H; k <= H; ++k) xo[k + H] = (uint32_t)wrap_col(i - k, nx, H);
-    // source rows j - k clamped into the channel, k in [-HN, HN]
+template <class SET, bool ALIGNED>
+struct Nbr2 {
+    static constexpr int H = SET::H, HN = SET::HN, V = SET::V;
     int rows[2 * HN + 1];
+    uint32_t col[2 * H + 1];
+    uint32_t rowstride;
+    int nx;
+    template <class SC>
+    __device__ __forceinline__ Nbr2(const SC &s, int i, int j) : nx(s.nx) {
+        rowstride = (uint32_t)s.nx * V;
 #pragma unroll
-    for (int k = -HN; k <= HN; ++k) rows[k + HN] = min(max(j - k, 0), ny - 1);
-    if constexpr (NR) raw[0] = src[aos_base<V>((uint32_t)j * nx + i)];
-    if constexpr (ALIGNED) {
-        // a row is a whole number of blocks: index = row base + column part
-        const uint32_t rowstride = (uint32_t)nx * V;
-        uint32_t cp[2 * H + 1];
+        for (int k = -HN; k <= HN; ++k) rows[k + HN] = min(max(j - k, 0), s.ny - 1);
 #pragma unroll
-        for (int k = 0; k < 2 * H + 1; ++k) cp[k] = (xo[k] >> 6) * (uint32_t)(64 * V) + (xo[k] & 63u);
-        for_pairs<SET::NP>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            constexpr int ex = SET::EX[p], ey = SET::EY[p];
-            raw[NR + 2 * p] = src[(uint32_t)rows[ey + HN] * rowstride + cp[ex + H] + 64 * (NR + 2 * p)];
-            raw[NR + 2 * p + 1] =
-                src[(uint32_t)rows[-ey + HN] * rowstride + cp[-ex + H] + 64 * (NR + 2 * p + 1)];
-        });
+        for (int k = -H; k <= H; ++k) {
+            const uint32_t x = (uint32_t)wrap_col(i - k, s.nx, H);
+            col[k + H] = ALIGNED ? (x >> 6) * (uint32_t)(64 * V) + (x & 63u) : x;
+        }
+    }
+    __device__ __forceinline__ uint32_t at(int dy, int dx) const {
+        if constexpr (ALIGNED)
+            return (uint32_t)rows[dy + HN] * rowstride + col[dx + H];
+        else
+            return aos_base<V>((uint32_t)rows[dy + HN] * (uint32_t)nx + col[dx + H]);
+    }
+};
+
+// Pull of the pre-collision values from the neighbours: population +e_p of x
+// comes from x - e_p, in slot -e_p (SWAP, kLocal) or slot +e_p (kDirect).
+// Rows are clamped: a wall slot reads a valid, unused value that complete2d
+// replaces.
+template <class SET, bool SWAP, class NB, typename T>
+__device__ __forceinline__ void read_pull(const T *A, const NB &nb, uint32_t own,
+                                          T (&raw)[SET::V]) {
+    constexpr int NR = SET::NR;
+    if constexpr (NR) raw[0] = A[own];
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int ex = SET::EX[p], ey = SET::EY[p];
+        raw[NR + 2 * p] = A[nb.at(ey, ex) + 64 * (SWAP ? NR + 2 * p + 1 : NR + 2 * p)];
+        raw[NR + 2 * p + 1] = A[nb.at(-ey, -ex) + 64 * (SWAP ? NR + 2 * p : NR + 2 * p + 1)];
+    });
+}
+
+// Home of post-collision population +e_p (PLUS) or -e_p of node x in the
+// kStreamed layout: slot +-e_p of the destination x +- e_p, or, when that lies
+// outside the channel, the node's own slot of the opposite velocity.
+template <class SET, int p, bool PLUS, class NB>
+__device__ __forceinline__ uint32_t home2d(const NB &nb, uint32_t own, int j, int ny) {
+    constexpr int NR = SET::NR, ex = SET::EX[p], ey = SET::EY[p];
+    constexpr int sy = PLUS ? ey : -ey, sx = PLUS ? ex : -ex;
+    constexpr int slot = PLUS ? NR + 2 * p : NR + 2 * p + 1, opp = PLUS ? NR + 2 * p + 1 : NR + 2 * p;
+    if constexpr (sy == 0) {
+        return nb.at(0, -sx) + 64 * slot;
     } else {
-        for_pairs<SET::NP>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            constexpr int ex = SET::EX[p], ey = SET::EY[p];
-            const uint32_t np_ = (uint32_t)rows[ey + HN] * nx + xo[ex + H];
-            const uint32_t nm_ = (uint32_t)rows[-ey + HN] * nx + xo[-ex + H];
-            raw[NR + 2 * p] = src[aos_base<V>(np_) + 64 * (NR + 2 * p)];
-            raw[NR + 2 * p + 1] = src[aos_base<V>(nm_) + 64 * (NR + 2 * p + 1)];
-        });
+        const bool inside = (unsigned)(j + sy) < (unsigned)ny;
+        return inside ? nb.at(-sy, -sx) + 64 * slot : own + 64 * opp;
     }
 }
 
-template <class SET, Storage S>
-__device__ __forceinline__ void gather2d(const typename St<S>::T *__restrict__ src,
-                                         const double *__restrict__ a_cur,
-                                         const PairTable<typename St<S>::R> &t,
-                                         const StepScalars<typename St<S>::R> &s, int i, int j,
-                                         typename St<S>::R (&d)[SET::V]) {
-    typename St<S>::T raw[SET::V];
-    issue2d<SET, S, false>(src, s, i, j, raw);
-    complete2d<SET, S>(raw, a_cur, t, s, i, j, d);
+// post-collision values -> kStreamed layout
+template <class SET, bool STREAM, class NB, typename T>
+__device__ __forceinline__ void write_gs(T *A, const NB &nb, uint32_t own, int j, int ny,
+                                         const T (&v)[SET::V]) {
+    constexpr int NR = SET::NR;
+    if constexpr (NR) store_pop<STREAM>(A + own, v[0]);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        store_pop<STREAM>(A + home2d<SET, p, true>(nb, own, j, ny), v[NR + 2 * p]);
+        store_pop<STREAM>(A + home2d<SET, p, false>(nb, own, j, ny), v[NR + 2 * p + 1]);
+    });
 }
 
-// store d[] and, on wall rows, the FP64 partial of what leaves next step
-template <class SET, Storage S, bool SRND, bool STREAM = false>
-__device__ __forceinline__ void scatter2d(typename St<S>::T *__restrict__ dst,
-                                          double *__restrict__ a_next,
-                                          const PairTable<typename St<S>::R> &t,
-                                          const StepScalars<typename St<S>::R> &s, int i, int j,
-                                          const typename St<S>::R (&d)[SET::V], uint32_t step) {
-    using T = typename St<S>::T;
-    const uint32_t n = (uint32_t)j * s.nx + i;
-    T v[SET::V];
-    encode_all<SET, S, SRND>(d, t, n, step, v);
-    T *out = dst + aos_base<SET::V>(n);
-#pragma unroll
-    for (int a = 0; a < SET::V; ++a) store_pop<STREAM>(out + 64 * a, v[a]);
-    wall_partials2d<SET, S>(v, t, s, i, j, a_next);
-}
+// Step kinds: the ping-pong pull (kDirect in pop, kDirect out to pop_out), and
+// the two in-place kinds (kLocal -> gather/scatter -> kStreamed; kStreamed ->
+// node-local -> kLocal).
+enum StepKind : int { kPingPong = 0, kGatherScatter = 1, kNodeLocal = 2 };
 
 // One block of 256 threads per tile of 256 consecutive nodes. Each thread
-// issues the pull loads of all its velocities before it decodes any of them,
-// so a wavefront has its whole gather in flight at once; the wall slots are
-// patched after the loads. ALIGNED (nx a multiple of 64) is compiled apart so
-// the common case carries no registers of the general index path. Measured on
-// MI355X against: a persistent grid with a two-stage register load pipeline
-// (occupancy 2), a persistent grid streaming the next tile's gather into LDS
-// with global_load_lds (LDS-limited to 8 waves per CU), 64-, 128- and 512-node
-// tiles, and register caps for 6, 7 or 8 waves per SIMD.
-template <class SET, Storage S, bool ALIGNED, bool STREAM>
+// issues all its loads before it decodes any, so a wavefront has its whole
+// gather in flight at once; wall slots are patched after the loads. The host
+// runs arrays of up to 512 MiB in place (on MI355X ~7% faster than ping-pong
+// for the 155 MB D2V37 channel: the array stays largely in the 256 MB
+// last-level cache) and larger ones ping-pong (~10% faster for the 1.3 GB
+// D3V39 duct). Also measured and rejected: a persistent grid with a two-stage
+// register load pipeline (occupancy 2), a persistent grid streaming the next
+// tile's gather into LDS with global_load_lds (LDS-limited to 8 waves per CU),
+// 64-, 128- and 512-node tiles, register caps for 6 to 8 waves per SIMD.
+template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND>
 __global__ __launch_bounds__(256)
 void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
               uint32_t step) {
@@ -127,19 +142,41 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     if (n >= (uint32_t)s.nodes) return;
     const int j = (int)(n / (uint32_t)s.nx);
     const int i = (int)(n - (uint32_t)j * s.nx);
+    T *A = (T *)b.pop;
+    const uint32_t own = aos_base<SET::V>(n);
     T raw[SET::V];
-    issue2d<SET, S, ALIGNED>((const T *)b.src, s, i, j, raw);
+    if constexpr (KIND == kNodeLocal) {
+        read_local<SET>(A, own, raw);
+    } else {
+        const Nbr2<SET, ALIGNED> nb(s, i, j);
+        read_pull<SET, KIND == kGatherScatter>(A, nb, own, raw);
+    }
     R d[SET::V];
     complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
     relax2d<SET, R>(d, t, s, t.c);
-    scatter2d<SET, S, true, STREAM>((T *)b.dst, b.a_next, t, s, i, j, d, step);
+    T v[SET::V];
+    encode_all<SET, S, true>(d, t, n, step, v);
+    if constexpr (KIND == kGatherScatter) {
+        // Each write address equals another velocity's read address; an opaque
+        // copy of (i, j) makes the compiler recompute them here instead of
+        // keeping ~V addresses live through the collision.
+        int iw = i, jw = j;
+        asm volatile("" : "+v"(iw), "+v"(jw));
+        const Nbr2<SET, ALIGNED> nb(s, iw, jw);
+        write_gs<SET, STREAM>(A, nb, own, jw, s.ny, v);
+    } else if constexpr (KIND == kNodeLocal) {
+        write_own<SET, true, STREAM>(A, own, v);
+    } else {
+        write_own<SET, false, STREAM>((T *)b.pop_out, own, v);
+    }
+    wall_partials2d<SET, S>(v, t, s, i, j, b.a_next);
 }
 
 // ---------------------------------------------------------------------------
 // observation: moments of the streamed state, FP64 partial sums per block
 // ---------------------------------------------------------------------------
 template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_observe2d(const void *src, const double *a_cur,
+__global__ __launch_bounds__(256) void k_observe2d(const void *pop, int layout, const double *a_cur,
                                                    double *rho_out, double *u_out, double *partial,
                                                    PairTable<typename St<S>::R> t,
                                                    StepScalars<typename St<S>::R> s) {
@@ -150,8 +187,20 @@ __global__ __launch_bounds__(256) void k_observe2d(const void *src, const double
     if (n < (uint32_t)s.nodes) {
         const int j = (int)(n / (uint32_t)s.nx);
         const int i = (int)(n - (uint32_t)j * s.nx);
+        const T *A = (const T *)pop;
+        const uint32_t own = aos_base<SET::V>(n);
+        T raw[SET::V];
+        if (layout == kStreamed) {
+            read_local<SET>(A, own, raw);
+        } else {
+            const Nbr2<SET, false> nb(s, i, j);
+            if (layout == kLocal)
+                read_pull<SET, true>(A, nb, own, raw);
+            else
+                read_pull<SET, false>(A, nb, own, raw);
+        }
         R d[SET::V];
-        gather2d<SET, S>((const T *)src, a_cur, t, s, i, j, d);
+        complete2d<SET, S>(raw, a_cur, t, s, i, j, d);
         const auto m = moments2d<SET, R>(d, s, t.c);
         rho_d = s.rho0d + (double)m.drho;
         ux_d = (double)m.ux;
@@ -166,11 +215,27 @@ __global__ __launch_bounds__(256) void k_observe2d(const void *src, const double
 }
 
 // ---------------------------------------------------------------------------
-// init / import / export
+// init / import (write the node's own slots: kLocal or kDirect) and export
 // ---------------------------------------------------------------------------
 template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_init2d(void *dst, double *a_out, const double *rho_in,
-                                                const double *u_in,
+__device__ __forceinline__ void store_own2d(typename St<S>::T *A, int layout, double *a_out,
+                                            const PairTable<typename St<S>::R> &t,
+                                            const StepScalars<typename St<S>::R> &s, int i, int j,
+                                            const typename St<S>::R (&d)[SET::V], uint32_t step) {
+    using T = typename St<S>::T;
+    const uint32_t n = (uint32_t)j * s.nx + i;
+    T v[SET::V];
+    encode_all<SET, S, false>(d, t, n, step, v);
+    if (layout == kLocal)
+        write_own<SET, true, false>(A, aos_base<SET::V>(n), v);
+    else
+        write_own<SET, false, false>(A, aos_base<SET::V>(n), v);
+    wall_partials2d<SET, S>(v, t, s, i, j, a_out);
+}
+
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_init2d(void *dst, int layout, double *a_out,
+                                                const double *rho_in, const double *u_in,
                                                 PairTable<typename St<S>::R> t,
                                                 StepScalars<typename St<S>::R> s, uint32_t step) {
     using R = typename St<S>::R;
@@ -187,12 +252,12 @@ __global__ __launch_bounds__(256) void k_init2d(void *dst, double *a_out, const 
     }
     R d[SET::V];
     equilibrium_dev<SET, R>(t, s, rho, ux, uy, R(0), d);
-    scatter2d<SET, S, false>((T *)dst, a_out, t, s, i, j, d, step);
+    store_own2d<SET, S>((T *)dst, layout, a_out, t, s, i, j, d, step);
 }
 
 template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_import2d(void *dst, double *a_out, const double *in,
-                                                  PairTable<typename St<S>::R> t,
+__global__ __launch_bounds__(256) void k_import2d(void *dst, int layout, double *a_out,
+                                                  const double *in, PairTable<typename St<S>::R> t,
                                                   StepScalars<typename St<S>::R> s, uint32_t step) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
@@ -202,7 +267,41 @@ __global__ __launch_bounds__(256) void k_import2d(void *dst, double *a_out, cons
     const int i = (int)(n - (uint32_t)j * s.nx);
     R d[SET::V];
     import_node<SET, R>(in, t, (uint32_t)s.nodes, n, d);
-    scatter2d<SET, S, false>((T *)dst, a_out, t, s, i, j, d, step);
+    store_own2d<SET, S>((T *)dst, layout, a_out, t, s, i, j, d, step);
+}
+
+// canonical FP64 export [alpha][node] of the post-collision populations
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_export2d(const void *pop, int layout, double *out,
+                                                  PairTable<typename St<S>::R> t,
+                                                  StepScalars<typename St<S>::R> s) {
+    using T = typename St<S>::T;
+    constexpr int NR = SET::NR;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    const int j = (int)(n / (uint32_t)s.nx);
+    const int i = (int)(n - (uint32_t)j * s.nx);
+    const uint32_t nodes = (uint32_t)s.nodes;
+    const T *A = (const T *)pop;
+    const uint32_t own = aos_base<SET::V>(n);
+    const Nbr2<SET, false> nb(s, i, j);
+    if constexpr (NR) out[n] = stored_value<S>(A[own], t.wrd0);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        uint32_t hp, hm;
+        if (layout == kLocal) {
+            hp = own + 64 * (NR + 2 * p + 1);
+            hm = own + 64 * (NR + 2 * p);
+        } else if (layout == kDirect) {
+            hp = own + 64 * (NR + 2 * p);
+            hm = own + 64 * (NR + 2 * p + 1);
+        } else {
+            hp = home2d<SET, p, true>(nb, own, j, s.ny);
+            hm = home2d<SET, p, false>(nb, own, j, s.ny);
+        }
+        out[(uint32_t)(NR + 2 * p) * nodes + n] = stored_value<S>(A[hp], t.wrd[p]);
+        out[(uint32_t)(NR + 2 * p + 1) * nodes + n] = stored_value<S>(A[hm], t.wrd[p]);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -211,50 +310,60 @@ __global__ __launch_bounds__(256) void k_import2d(void *dst, double *a_out, cons
 template <class SET, Storage S>
 struct L2 {
     using R = typename St<S>::R;
+    template <int KIND>
+    static void launch_step(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
+                            hipStream_t st, uint32_t stp) {
+        const dim3 g(blocks_for(s.nodes)), bl(256);
+        if (s.aligned_rows && s.stream_stores)
+            hipLaunchKernelGGL((k_step2d<SET, S, true, true, KIND>), g, bl, 0, st, b, t, s, stp);
+        else if (s.aligned_rows)
+            hipLaunchKernelGGL((k_step2d<SET, S, true, false, KIND>), g, bl, 0, st, b, t, s, stp);
+        else
+            hipLaunchKernelGGL((k_step2d<SET, S, false, false, KIND>), g, bl, 0, st, b, t, s, stp);
+    }
     static int step(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
                     uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        const dim3 g(blocks_for(s.nodes)), bl(256);
-        if (s.aligned_rows && s.stream_stores)
-            hipLaunchKernelGGL((k_step2d<SET, S, true, true>), g, bl, 0, st, b, t, s, stp);
-        else if (s.aligned_rows)
-            hipLaunchKernelGGL((k_step2d<SET, S, true, false>), g, bl, 0, st, b, t, s, stp);
+        if (b.layout == kLocal)
+            launch_step<kGatherScatter>(b, t, s, st, stp);
+        else if (b.layout == kStreamed)
+            launch_step<kNodeLocal>(b, t, s, st, stp);
         else
-            hipLaunchKernelGGL((k_step2d<SET, S, false, false>), g, bl, 0, st, b, t, s, stp);
+            launch_step<kPingPong>(b, t, s, st, stp);
         return hip_ok(hipGetLastError(), "step kernel launch");
     }
-    static int init(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
-                    const void *sc, hipStream_t st, uint32_t stp) {
+    static int init(void *dst, int layout, double *a_out, const double *rho, const double *u,
+                    const void *tab, const void *sc, hipStream_t st, uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_init2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, dst,
-                           a_out, rho, u, t, s, stp);
+                           layout, a_out, rho, u, t, s, stp);
         return hip_ok(hipGetLastError(), "init kernel launch");
     }
-    static int observe(const void *src, const double *a_cur, const double * /*invd*/, double *rho,
-                       double *u, double *partial, const void *tab, const void *sc,
+    static int observe(const void *pop, int layout, const double *a_cur, const double * /*invd*/,
+                       double *rho, double *u, double *partial, const void *tab, const void *sc,
                        hipStream_t st) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_observe2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,
-                           src, a_cur, rho, u, partial, t, s);
+                           pop, layout, a_cur, rho, u, partial, t, s);
         return hip_ok(hipGetLastError(), "observe kernel launch");
     }
-    static int exportp(const void *src, double *out, const void *tab, const void *sc,
+    static int exportp(const void *pop, int layout, double *out, const void *tab, const void *sc,
                        hipStream_t st) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        hipLaunchKernelGGL((k_export<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, src,
-                           out, t, s);
+        hipLaunchKernelGGL((k_export2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, pop,
+                           layout, out, t, s);
         return hip_ok(hipGetLastError(), "export kernel launch");
     }
-    static int importp(void *dst, double *a_out, const double *in, const void *tab, const void *sc,
-                       hipStream_t st, uint32_t stp) {
+    static int importp(void *dst, int layout, double *a_out, const double *in, const void *tab,
+                       const void *sc, hipStream_t st, uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_import2d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,
-                           dst, a_out, in, t, s, stp);
+                           dst, layout, a_out, in, t, s, stp);
         return hip_ok(hipGetLastError(), "import kernel launch");
     }
     static constexpr Launch table{&step, &init, &observe, &exportp, &importp};

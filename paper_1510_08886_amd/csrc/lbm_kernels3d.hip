@@ -1,10 +1,11 @@
 // HIP kernels for gfx950: the fused pull-stream + diffuse Maxwell wall + BGK
 // update (Eq. nm.8) of a 3D duct: x periodic, walls normal to y and z.
 //
-// Node n = (k * ny + j) * nx + i; populations in 64-node blocks (aos_base).
-// Pull sources are clamped into the duct in y and z so every load is valid;
-// the populations whose source lies outside are replaced by the diffuse-wall
-// populations rho_eff w (1 - dt/2 g.xi) of Eqs. nm.14 / nm.15.
+// Node n = (k * ny + j) * nx + i; populations in 64-node blocks (aos_base), one
+// array updated in place (PopLayout). Neighbour accesses are clamped into the
+// duct in y and z so every access is valid; the populations whose source lies
+// outside are replaced by the diffuse-wall populations rho_eff w (1 - dt/2
+// g.xi) of Eqs. nm.14 / nm.15.
 //
 // Wall elements: an unknown slot (x, alpha), whose virtual source x - e_alpha
 // lies outside, and the absorbed population (x, -alpha) cross the same
@@ -155,47 +156,87 @@ __device__ __forceinline__ int first_face(int j, int k, int vy, int vz, bool oy,
 }
 
 // ---------------------------------------------------------------------------
-// gather
+// neighbour addressing of the in-place array (PopLayout): element index of
+// slot 0 of node (k - dz, j - dy, i - dx), |dz|, |dy| <= HN, |dx| <= H, rows
+// clamped into the duct (every address valid), x periodic
 // ---------------------------------------------------------------------------
-template <class SET, Storage S, bool ALIGNED>
-__device__ __forceinline__ void issue3d(const typename St<S>::T *__restrict__ src,
-                                        const StepScalars<typename St<S>::R> &s, int i, int j,
-                                        int k, typename St<S>::T (&raw)[SET::V]) {
-    constexpr int NR = SET::NR, H = SET::H, HN = SET::HN, V = SET::V;
-    const int nx = s.nx, ny = s.ny, nz = s.nz;
-    uint32_t xo[2 * H + 1];
-#pragma unroll
-    for (int q = -H; q <= H; ++q) xo[q + H] = (uint32_t)wrap_col(i - q, nx, H);
+template <class SET, bool ALIGNED>
+struct Nbr3 {
+    static constexpr int H = SET::H, HN = SET::HN, V = SET::V;
     int ry[2 * HN + 1], rz[2 * HN + 1];
+    uint32_t col[2 * H + 1];
+    uint32_t rowstride;
+    int nx, ny;
+    template <class SC>
+    __device__ __forceinline__ Nbr3(const SC &s, int i, int j, int k) : nx(s.nx), ny(s.ny) {
+        rowstride = (uint32_t)s.nx * V;
 #pragma unroll
-    for (int q = -HN; q <= HN; ++q) {
-        ry[q + HN] = min(max(j - q, 0), ny - 1);
-        rz[q + HN] = min(max(k - q, 0), nz - 1);
+        for (int q = -HN; q <= HN; ++q) {
+            ry[q + HN] = min(max(j - q, 0), s.ny - 1);
+            rz[q + HN] = min(max(k - q, 0), s.nz - 1);
+        }
+#pragma unroll
+        for (int q = -H; q <= H; ++q) {
+            const uint32_t x = (uint32_t)wrap_col(i - q, s.nx, H);
+            col[q + H] = ALIGNED ? (x >> 6) * (uint32_t)(64 * V) + (x & 63u) : x;
+        }
     }
-    if constexpr (NR) raw[0] = src[aos_base<V>(((uint32_t)k * ny + j) * nx + i)];
-    if constexpr (ALIGNED) {
-        const uint32_t rowstride = (uint32_t)nx * V;
-        uint32_t cp[2 * H + 1];
-#pragma unroll
-        for (int q = 0; q < 2 * H + 1; ++q) cp[q] = (xo[q] >> 6) * (uint32_t)(64 * V) + (xo[q] & 63u);
-        for_pairs<SET::NP>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
-            const uint32_t rowp = (uint32_t)rz[ez + HN] * ny + ry[ey + HN];
-            const uint32_t rowm = (uint32_t)rz[-ez + HN] * ny + ry[-ey + HN];
-            raw[NR + 2 * p] = src[rowp * rowstride + cp[ex + H] + 64 * (NR + 2 * p)];
-            raw[NR + 2 * p + 1] = src[rowm * rowstride + cp[-ex + H] + 64 * (NR + 2 * p + 1)];
-        });
+    __device__ __forceinline__ uint32_t at(int dz, int dy, int dx) const {
+        const uint32_t row = (uint32_t)rz[dz + HN] * (uint32_t)ny + (uint32_t)ry[dy + HN];
+        if constexpr (ALIGNED)
+            return row * rowstride + col[dx + H];
+        else
+            return aos_base<V>(row * (uint32_t)nx + col[dx + H]);
+    }
+};
+
+// pull of the pre-collision values: population +e_p of x from x - e_p, in
+// slot -e_p (SWAP, kLocal) or +e_p (kDirect)
+template <class SET, bool SWAP, class NB, typename T>
+__device__ __forceinline__ void read_pull3(const T *A, const NB &nb, uint32_t own,
+                                           T (&raw)[SET::V]) {
+    constexpr int NR = SET::NR;
+    if constexpr (NR) raw[0] = A[own];
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
+        raw[NR + 2 * p] = A[nb.at(ez, ey, ex) + 64 * (SWAP ? NR + 2 * p + 1 : NR + 2 * p)];
+        raw[NR + 2 * p + 1] = A[nb.at(-ez, -ey, -ex) + 64 * (SWAP ? NR + 2 * p : NR + 2 * p + 1)];
+    });
+}
+
+// home of post-collision population +e_p (PLUS) or -e_p of node x in the
+// kStreamed layout: slot +-e_p of x +- e_p, or the node's own slot of the
+// opposite velocity when x +- e_p lies outside the duct
+template <class SET, int p, bool PLUS, class NB>
+__device__ __forceinline__ uint32_t home3d(const NB &nb, uint32_t own, int j, int k, int ny,
+                                           int nz) {
+    constexpr int NR = SET::NR;
+    constexpr int sx = PLUS ? SET::EX[p] : -SET::EX[p];
+    constexpr int sy = PLUS ? SET::EY[p] : -SET::EY[p];
+    constexpr int sz = PLUS ? SET::EZ[p] : -SET::EZ[p];
+    constexpr int slot = PLUS ? NR + 2 * p : NR + 2 * p + 1, opp = PLUS ? NR + 2 * p + 1 : NR + 2 * p;
+    if constexpr (sy == 0 && sz == 0) {
+        return nb.at(0, 0, -sx) + 64 * slot;
     } else {
-        for_pairs<SET::NP>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            constexpr int ex = SET::EX[p], ey = SET::EY[p], ez = SET::EZ[p];
-            const uint32_t np_ = ((uint32_t)rz[ez + HN] * ny + ry[ey + HN]) * nx + xo[ex + H];
-            const uint32_t nm_ = ((uint32_t)rz[-ez + HN] * ny + ry[-ey + HN]) * nx + xo[-ex + H];
-            raw[NR + 2 * p] = src[aos_base<V>(np_) + 64 * (NR + 2 * p)];
-            raw[NR + 2 * p + 1] = src[aos_base<V>(nm_) + 64 * (NR + 2 * p + 1)];
-        });
+        bool inside = true;
+        if constexpr (sy != 0) inside = inside && (unsigned)(j + sy) < (unsigned)ny;
+        if constexpr (sz != 0) inside = inside && (unsigned)(k + sz) < (unsigned)nz;
+        return inside ? nb.at(-sz, -sy, -sx) + 64 * slot : own + 64 * opp;
     }
+}
+
+// post-collision values -> kStreamed layout
+template <class SET, bool STREAM, class NB, typename T>
+__device__ __forceinline__ void write_gs3(T *A, const NB &nb, uint32_t own, int j, int k, int ny,
+                                          int nz, const T (&v)[SET::V]) {
+    constexpr int NR = SET::NR;
+    if constexpr (NR) store_pop<STREAM>(A + own, v[0]);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        store_pop<STREAM>(A + home3d<SET, p, true>(nb, own, j, k, ny, nz), v[NR + 2 * p]);
+        store_pop<STREAM>(A + home3d<SET, p, false>(nb, own, j, k, ny, nz), v[NR + 2 * p + 1]);
+    });
 }
 
 template <class SET, Storage S>
@@ -285,23 +326,6 @@ __device__ __forceinline__ void wall_partials3d(const typename St<S>::T (&v)[SET
     if (zhi) a_next[kZHi * fs + (int64_t)(nz - 1 - k) * epz + (int64_t)j * nx + i] = acc[kZHi];
 }
 
-template <class SET, Storage S, bool SRND, bool STREAM = false>
-__device__ __forceinline__ void scatter3d(typename St<S>::T *__restrict__ dst,
-                                          double *__restrict__ a_next,
-                                          const PairTable<typename St<S>::R> &t,
-                                          const StepScalars<typename St<S>::R> &s, int i, int j,
-                                          int k, const typename St<S>::R (&d)[SET::V],
-                                          uint32_t step) {
-    using T = typename St<S>::T;
-    const uint32_t n = ((uint32_t)k * s.ny + j) * s.nx + i;
-    T v[SET::V];
-    encode_all<SET, S, SRND>(d, t, n, step, v);
-    T *out = dst + aos_base<SET::V>(n);
-#pragma unroll
-    for (int a = 0; a < SET::V; ++a) store_pop<STREAM>(out + 64 * a, v[a]);
-    wall_partials3d<SET, S>(v, t, s, i, j, k, a_next);
-}
-
 __device__ __forceinline__ void node_ijk(uint32_t n, int nx, int ny, int &i, int &j, int &k) {
     const uint32_t row = n / (uint32_t)nx;
     i = (int)(n - row * nx);
@@ -309,8 +333,13 @@ __device__ __forceinline__ void node_ijk(uint32_t n, int nx, int ny, int &i, int
     j = (int)(row - (uint32_t)k * ny);
 }
 
-// ALIGNED (nx a multiple of 64) is compiled apart.
-template <class SET, Storage S, bool ALIGNED, bool STREAM>
+// step kinds (as for the channel): ping-pong pull (kDirect), and in place
+// gather/scatter (kLocal -> kStreamed) and node-local (kStreamed -> kLocal)
+enum StepKind3 : int { kPingPong3 = 0, kGatherScatter3 = 1, kNodeLocal3 = 2 };
+
+// One 256-thread block per 256 consecutive nodes. ALIGNED (nx a multiple of
+// 64) is compiled apart.
+template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND>
 __global__ __launch_bounds__(256)
 void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
               uint32_t step) {
@@ -320,16 +349,37 @@ void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     if (n >= (uint32_t)s.nodes) return;
     int i, j, k;
     node_ijk(n, s.nx, s.ny, i, j, k);
+    T *A = (T *)b.pop;
+    const uint32_t own = aos_base<SET::V>(n);
     T raw[SET::V];
-    issue3d<SET, S, ALIGNED>((const T *)b.src, s, i, j, k, raw);
+    if constexpr (KIND == kNodeLocal3) {
+        read_local<SET>(A, own, raw);
+    } else {
+        const Nbr3<SET, ALIGNED> nb(s, i, j, k);
+        read_pull3<SET, KIND == kGatherScatter3>(A, nb, own, raw);
+    }
     R d[SET::V];
     complete3d<SET, S>(raw, b.a_cur, b.invd, t, s, i, j, k, d);
     relax3d<SET, R>(d, t, s, t.c);
-    scatter3d<SET, S, true, STREAM>((T *)b.dst, b.a_next, t, s, i, j, k, d, step);
+    T v[SET::V];
+    encode_all<SET, S, true>(d, t, n, step, v);
+    if constexpr (KIND == kGatherScatter3) {
+        // recompute the write addresses (equal to read addresses of other
+        // velocities) rather than keep them live through the collision
+        int iw = i, jw = j, kw = k;
+        asm volatile("" : "+v"(iw), "+v"(jw), "+v"(kw));
+        const Nbr3<SET, ALIGNED> nb(s, iw, jw, kw);
+        write_gs3<SET, STREAM>(A, nb, own, jw, kw, s.ny, s.nz, v);
+    } else if constexpr (KIND == kNodeLocal3) {
+        write_own<SET, true, STREAM>(A, own, v);
+    } else {
+        write_own<SET, false, STREAM>((T *)b.pop_out, own, v);
+    }
+    wall_partials3d<SET, S>(v, t, s, i, j, k, b.a_next);
 }
 
 template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_observe3d(const void *src, const double *a_cur,
+__global__ __launch_bounds__(256) void k_observe3d(const void *pop, int layout, const double *a_cur,
                                                    const double *invd, double *rho_out,
                                                    double *u_out, double *partial,
                                                    PairTable<typename St<S>::R> t,
@@ -341,8 +391,18 @@ __global__ __launch_bounds__(256) void k_observe3d(const void *src, const double
     if (n < (uint32_t)s.nodes) {
         int i, j, k;
         node_ijk(n, s.nx, s.ny, i, j, k);
+        const T *A = (const T *)pop;
+        const uint32_t own = aos_base<SET::V>(n);
         T raw[SET::V];
-        issue3d<SET, S, false>((const T *)src, s, i, j, k, raw);
+        if (layout == kStreamed) {
+            read_local<SET>(A, own, raw);
+        } else {
+            const Nbr3<SET, false> nb(s, i, j, k);
+            if (layout == kLocal)
+                read_pull3<SET, true>(A, nb, own, raw);
+            else
+                read_pull3<SET, false>(A, nb, own, raw);
+        }
         R d[SET::V];
         complete3d<SET, S>(raw, a_cur, invd, t, s, i, j, k, d);
         const auto m = moments3d<SET, R>(d, s, t.c);
@@ -358,9 +418,27 @@ __global__ __launch_bounds__(256) void k_observe3d(const void *src, const double
     block_sum2(ux_d, rho_d, partial);
 }
 
+// init / import: write the node's own slots (kLocal or kDirect)
 template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_init3d(void *dst, double *a_out, const double *rho_in,
-                                                const double *u_in,
+__device__ __forceinline__ void store_own3d(typename St<S>::T *A, int layout, double *a_out,
+                                              const PairTable<typename St<S>::R> &t,
+                                              const StepScalars<typename St<S>::R> &s, int i,
+                                              int j, int k, const typename St<S>::R (&d)[SET::V],
+                                              uint32_t step) {
+    using T = typename St<S>::T;
+    const uint32_t n = ((uint32_t)k * s.ny + j) * s.nx + i;
+    T v[SET::V];
+    encode_all<SET, S, false>(d, t, n, step, v);
+    if (layout == kLocal)
+        write_own<SET, true, false>(A, aos_base<SET::V>(n), v);
+    else
+        write_own<SET, false, false>(A, aos_base<SET::V>(n), v);
+    wall_partials3d<SET, S>(v, t, s, i, j, k, a_out);
+}
+
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_init3d(void *dst, int layout, double *a_out,
+                                                const double *rho_in, const double *u_in,
                                                 PairTable<typename St<S>::R> t,
                                                 StepScalars<typename St<S>::R> s, uint32_t step) {
     using R = typename St<S>::R;
@@ -378,11 +456,12 @@ __global__ __launch_bounds__(256) void k_init3d(void *dst, double *a_out, const 
     }
     R d[SET::V];
     equilibrium_dev<SET, R>(t, s, rho, ux, uy, uz, d);
-    scatter3d<SET, S, false>((T *)dst, a_out, t, s, i, j, k, d, step);
+    store_own3d<SET, S>((T *)dst, layout, a_out, t, s, i, j, k, d, step);
 }
 
 template <class SET, Storage S>
-__global__ __launch_bounds__(256) void k_import3d(void *dst, double *a_out, const double *in,
+__global__ __launch_bounds__(256) void k_import3d(void *dst, int layout, double *a_out,
+                                                  const double *in,
                                                   PairTable<typename St<S>::R> t,
                                                   StepScalars<typename St<S>::R> s, uint32_t step) {
     using R = typename St<S>::R;
@@ -393,56 +472,100 @@ __global__ __launch_bounds__(256) void k_import3d(void *dst, double *a_out, cons
     node_ijk(n, s.nx, s.ny, i, j, k);
     R d[SET::V];
     import_node<SET, R>(in, t, (uint32_t)s.nodes, n, d);
-    scatter3d<SET, S, false>((T *)dst, a_out, t, s, i, j, k, d, step);
+    store_own3d<SET, S>((T *)dst, layout, a_out, t, s, i, j, k, d, step);
+}
+
+// canonical FP64 export [alpha][node] of the post-collision populations
+template <class SET, Storage S>
+__global__ __launch_bounds__(256) void k_export3d(const void *pop, int layout, double *out,
+                                                  PairTable<typename St<S>::R> t,
+                                                  StepScalars<typename St<S>::R> s) {
+    using T = typename St<S>::T;
+    constexpr int NR = SET::NR;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (uint32_t)s.nodes) return;
+    int i, j, k;
+    node_ijk(n, s.nx, s.ny, i, j, k);
+    const uint32_t nodes = (uint32_t)s.nodes;
+    const T *A = (const T *)pop;
+    const uint32_t own = aos_base<SET::V>(n);
+    const Nbr3<SET, false> nb(s, i, j, k);
+    if constexpr (NR) out[n] = stored_value<S>(A[own], t.wrd0);
+    for_pairs<SET::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        uint32_t hp, hm;
+        if (layout == kLocal) {
+            hp = own + 64 * (NR + 2 * p + 1);
+            hm = own + 64 * (NR + 2 * p);
+        } else if (layout == kDirect) {
+            hp = own + 64 * (NR + 2 * p);
+            hm = own + 64 * (NR + 2 * p + 1);
+        } else {
+            hp = home3d<SET, p, true>(nb, own, j, k, s.ny, s.nz);
+            hm = home3d<SET, p, false>(nb, own, j, k, s.ny, s.nz);
+        }
+        out[(uint32_t)(NR + 2 * p) * nodes + n] = stored_value<S>(A[hp], t.wrd[p]);
+        out[(uint32_t)(NR + 2 * p + 1) * nodes + n] = stored_value<S>(A[hm], t.wrd[p]);
+    });
 }
 
 template <class SET, Storage S>
 struct L3 {
     using R = typename St<S>::R;
+    template <int KIND>
+    static void launch_step(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
+                            hipStream_t st, uint32_t stp) {
+        const dim3 g(blocks_for(s.nodes)), bl(256);
+        if (s.aligned_rows && s.stream_stores)
+            hipLaunchKernelGGL((k_step3d<SET, S, true, true, KIND>), g, bl, 0, st, b, t, s, stp);
+        else if (s.aligned_rows)
+            hipLaunchKernelGGL((k_step3d<SET, S, true, false, KIND>), g, bl, 0, st, b, t, s, stp);
+        else
+            hipLaunchKernelGGL((k_step3d<SET, S, false, false, KIND>), g, bl, 0, st, b, t, s, stp);
+    }
     static int step(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
                     uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        const dim3 g(blocks_for(s.nodes)), bl(256);
-        if (s.aligned_rows && s.stream_stores)
-            hipLaunchKernelGGL((k_step3d<SET, S, true, true>), g, bl, 0, st, b, t, s, stp);
-        else if (s.aligned_rows)
-            hipLaunchKernelGGL((k_step3d<SET, S, true, false>), g, bl, 0, st, b, t, s, stp);
+        if (b.layout == kLocal)
+            launch_step<kGatherScatter3>(b, t, s, st, stp);
+        else if (b.layout == kStreamed)
+            launch_step<kNodeLocal3>(b, t, s, st, stp);
         else
-            hipLaunchKernelGGL((k_step3d<SET, S, false, false>), g, bl, 0, st, b, t, s, stp);
+            launch_step<kPingPong3>(b, t, s, st, stp);
         return hip_ok(hipGetLastError(), "3D step kernel launch");
     }
-    static int init(void *dst, double *a_out, const double *rho, const double *u, const void *tab,
-                    const void *sc, hipStream_t st, uint32_t stp) {
+    static int init(void *dst, int layout, double *a_out, const double *rho, const double *u,
+                    const void *tab, const void *sc, hipStream_t st, uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_init3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, dst,
-                           a_out, rho, u, t, s, stp);
+                           layout, a_out, rho, u, t, s, stp);
         return hip_ok(hipGetLastError(), "3D init kernel launch");
     }
-    static int observe(const void *src, const double *a_cur, const double *invd, double *rho,
-                       double *u, double *partial, const void *tab, const void *sc,
+    static int observe(const void *pop, int layout, const double *a_cur, const double *invd,
+                       double *rho, double *u, double *partial, const void *tab, const void *sc,
                        hipStream_t st) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_observe3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,
-                           src, a_cur, invd, rho, u, partial, t, s);
+                           pop, layout, a_cur, invd, rho, u, partial, t, s);
         return hip_ok(hipGetLastError(), "3D observe kernel launch");
     }
-    static int exportp(const void *src, double *out, const void *tab, const void *sc,
+    static int exportp(const void *pop, int layout, double *out, const void *tab, const void *sc,
                        hipStream_t st) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
-        hipLaunchKernelGGL((k_export<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, src,
-                           out, t, s);
-        return hip_ok(hipGetLastError(), "export kernel launch");
+        hipLaunchKernelGGL((k_export3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st, pop,
+                           layout, out, t, s);
+        return hip_ok(hipGetLastError(), "3D export kernel launch");
     }
-    static int importp(void *dst, double *a_out, const double *in, const void *tab, const void *sc,
-                       hipStream_t st, uint32_t stp) {
+    static int importp(void *dst, int layout, double *a_out, const double *in, const void *tab,
+                       const void *sc, hipStream_t st, uint32_t stp) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         hipLaunchKernelGGL((k_import3d<SET, S>), dim3(blocks_for(s.nodes)), dim3(256), 0, st,
-                           dst, a_out, in, t, s, stp);
+                           dst, layout, a_out, in, t, s, stp);
         return hip_ok(hipGetLastError(), "3D import kernel launch");
     }
     static constexpr Launch table{&step, &init, &observe, &exportp, &importp};

@@ -293,11 +293,11 @@ class Solver:
         self.dvm, self.prob = dvm, prob
         self.device = torch.device(device)
         pop_b, scr_b = state_bytes(dvm, prob)
-        # 256-byte aligned allocations from torch's allocator
-        self.pop_a = torch.empty(pop_b, dtype=torch.uint8, device=self.device)
-        self.pop_b = torch.empty(pop_b, dtype=torch.uint8, device=self.device)
+        # 256-byte aligned allocations from torch's allocator; one population
+        # array (the library updates it in place)
+        self.pop = torch.empty(pop_b, dtype=torch.uint8, device=self.device)
         self.scratch = torch.empty(scr_b, dtype=torch.uint8, device=self.device)
-        for t in (self.pop_a, self.pop_b, self.scratch):
+        for t in (self.pop, self.scratch):
             if t.data_ptr() % 256:
                 raise RuntimeError("device allocation is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -306,8 +306,8 @@ class Solver:
         self.shape = ((prob.nz, prob.ny, prob.nx) if prob.dim == 3 else (prob.ny, prob.nx))
         pc = prob.to_c()
         h = _P()
-        check(lib().lbm_solver_create(dvm._h, ctypes.byref(pc), _ptr(self.pop_a),
-                                      _ptr(self.pop_b), _ptr(self.scratch), scr_b,
+        check(lib().lbm_solver_create(dvm._h, ctypes.byref(pc), _ptr(self.pop), None,
+                                      _ptr(self.scratch), scr_b,
                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
               "lbm_solver_create")
         self._h = h

@@ -115,3 +115,25 @@ def test_scattering_stencil_duct_low_precision():
         o.run(150)
         got, want = g.observe()["mdot"], o.observe()["mdot"]
         assert abs(got - want) <= tol * abs(want), (storage, got, want)
+
+
+def test_f64_pingpong_path_elementwise():
+    """Above 512 MiB of populations the library steps two copies ping-pong
+    instead of one array in place: a 64 x 166 x 166 D3V39 FP64 duct (about
+    550 MB) from a random state, against the oracle element by element after
+    one and after two steps."""
+    from paper_1510_08886_amd import lbm
+    nx, ny, nz = 64, 166, 166
+    d = lbm.Dvm.named("D3V39")
+    prob = lbm.Problem(dim=3, nx=nx, ny=ny, nz=nz, kn=0.1, ma=1e-2, hermite_order=3, storage="f64")
+    pop_bytes, _ = lbm.state_bytes(d, prob)
+    assert pop_bytes >= 2 * 39 * nx * ny * nz * 8       # two copies: the ping-pong path
+    nodes = nx * ny * nz
+    rho, u = wl.random_state(nodes, 3, seed=5, amp=1e-2)
+    d, g, o = make_pair("D3V39", 3, nx, ny, nz, kn=0.1, ma=1e-2, rho=rho, u=u)
+    for steps in (1, 1):
+        g.run(steps)
+        o.run(steps, nthreads=16)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po)) <= 1e-14
+    assert abs(g.observe()["mdot"] - o.observe()["mdot"]) <= 1e-12 * abs(o.observe()["mdot"])
