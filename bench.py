@@ -26,11 +26,15 @@ import lbm_workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_step_d2v37_f32_2048x512.json"
+# what the headline kernels' traffic depends on: their sources, the build flags
+# and the host's choice between in-place and ping-pong stepping
 KERNEL_SOURCES = ["paper_1510_08886_amd/csrc/lbm_kernels.hip",
                   "paper_1510_08886_amd/csrc/lbm_device.h",
                   "paper_1510_08886_amd/csrc/lbm_node2d.h",
                   "paper_1510_08886_amd/csrc/lbm_internal.h",
-                  "paper_1510_08886_amd/csrc/lbm_sets.h"]
+                  "paper_1510_08886_amd/csrc/lbm_sets.h",
+                  "paper_1510_08886_amd/csrc/lbm_api.cpp",
+                  "paper_1510_08886_amd/build.py"]
 
 
 def kernel_hash() -> str:
