@@ -109,3 +109,22 @@ def test_state_bytes_layout():
     pop16, _ = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
                                               storage="f16dev"))
     assert pop16 == pop // 2
+
+
+def test_state_bytes_in_place_up_to_512_mib_then_two_copies():
+    """One population array (stepped in place) while a copy is at most 512 MiB,
+    two copies (ping-pong) above: the 2048 x 512 D2V37 FP32 channel needs one
+    155 MB array, the 128 x 256 x 256 D3V39 FP32 duct two 1.3 GB copies."""
+    d2 = lbm.Dvm.named("D2V37")
+    pop, _ = lbm.state_bytes(d2, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
+                                             storage="f32"))
+    assert pop == 37 * 2048 * 512 * 4
+    d3 = lbm.Dvm.named("D3V39")
+    one = 39 * 128 * 256 * 256 * 4
+    pop3, _ = lbm.state_bytes(d3, lbm.Problem(dim=3, nx=128, ny=256, nz=256, kn=0.1,
+                                              hermite_order=3, storage="f32"))
+    assert pop3 == 2 * one
+    # just below the threshold: one copy
+    pop4, _ = lbm.state_bytes(d3, lbm.Problem(dim=3, nx=64, ny=160, nz=160, kn=0.1,
+                                              hermite_order=3, storage="f64"))
+    assert pop4 == 39 * 64 * 160 * 160 * 8 and pop4 <= 512 << 20
