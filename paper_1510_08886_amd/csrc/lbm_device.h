@@ -207,7 +207,12 @@ __device__ __forceinline__ R lin3(R x, R y, R z) {
         return addk<C>(addk<B>(mulk<A>(x), y), z);
 }
 
-// encode all velocities of one node (stochastic rounding keyed by node, step)
+// Encode all velocities of one node. Stochastic rounding (half storage in time
+// steps) takes one PCG hash of (node, step) and gives slot alpha the top 13
+// bits of key + alpha * 0x9E3779B9, a Weyl sequence with the golden-ratio
+// increment: each offset is uniform, and the offsets of one node are evenly
+// spread rather than independent, which keeps a node's rounding errors from
+// adding up. Two operations per slot instead of a hash per slot.
 template <class SET, Storage S, bool SRND>
 __device__ __forceinline__ void encode_all(const typename St<S>::R (&d)[SET::V],
                                            const PairTable<typename St<S>::R> &t, uint32_t n,
@@ -215,13 +220,13 @@ __device__ __forceinline__ void encode_all(const typename St<S>::R (&d)[SET::V],
     constexpr int NR = SET::NR;
     uint32_t key = 0;
     if constexpr (S == Storage::F16DEV && SRND) key = node_key(n, step);
-    if constexpr (NR) v[0] = encode_dev<S, SRND>(d[0], t.wr00, t.inv_wr00, key >> 19);
+    auto rnd = [&](int slot) -> uint32_t { return (key + (uint32_t)slot * 0x9E3779B9u) >> 19; };
+    if constexpr (NR) v[0] = encode_dev<S, SRND>(d[0], t.wr00, t.inv_wr00, rnd(0));
     for_pairs<SET::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        uint32_t r = 0;
-        if constexpr (S == Storage::F16DEV && SRND) r = pcg_hash(key + (uint32_t)p);
-        v[NR + 2 * p] = encode_dev<S, SRND>(d[NR + 2 * p], t.wr0[p], t.inv_wr0[p], r);
-        v[NR + 2 * p + 1] = encode_dev<S, SRND>(d[NR + 2 * p + 1], t.wr0[p], t.inv_wr0[p], r >> 16);
+        v[NR + 2 * p] = encode_dev<S, SRND>(d[NR + 2 * p], t.wr0[p], t.inv_wr0[p], rnd(NR + 2 * p));
+        v[NR + 2 * p + 1] =
+            encode_dev<S, SRND>(d[NR + 2 * p + 1], t.wr0[p], t.inv_wr0[p], rnd(NR + 2 * p + 1));
     });
 }
 
