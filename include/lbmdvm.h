@@ -178,7 +178,8 @@ int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, size_t *pop
  * copies, stepped ping-pong. pop_b is not used and may be NULL.
  * Validation (LBM_E_INVALID): ny (and nz in 3D) >= the largest |e_n|;
  * 2 <= N <= (Q+1)/2; kn > 0; g.n = 0; sizes positive. accommodation != 1 gives
- * LBM_E_UNSUPPORTED, as does a velocity count without a compiled kernel. */
+ * LBM_E_UNSUPPORTED, as do N > 5 and a velocity set without a compiled kernel
+ * (N = 5 is compiled for the sets of quadrature order 9). */
 int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
                       void *pop_b, void *scratch, size_t scratch_bytes, void *stream,
                       lbm_solver_t **out);
@@ -265,7 +266,8 @@ int lbm_batch_create(int max_slots, int storage, void *pool, size_t pool_bytes, 
 int lbm_batch_destroy(lbm_batch_t *b);
 
 /* Queue one channel solve: prob->dim = 2, prob->nx = 1, prob->storage equal
- * to the batch's; the DVM must have a compiled kernel. It runs from the rest
+ * to the batch's, Hermite order N <= 4 (else LBM_E_UNSUPPORTED); the DVM must
+ * be D2V17 or D2V37. It runs from the rest
  * state rho0 w until |mdot_k - mdot_{k-1}| < tol |mdot_k| with mdot evaluated
  * every check_every steps, or until max_steps. LBM_E_NO_MEMORY if it can
  * never fit the pool or the LDS of one workgroup. */

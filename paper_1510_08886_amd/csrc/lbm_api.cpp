@@ -116,8 +116,8 @@ int validate(const Dvm &d, const lbm_problem_t &p) {
         return fail(LBM_E_INVALID, "ny (and nz) must be at least the largest wall-normal |e|");
     if (p.hermite_order < 2 || p.hermite_order > (d.Q + 1) / 2)
         return fail(LBM_E_INVALID, "hermite order must satisfy 2 <= N <= (Q+1)/2");
-    if (p.hermite_order > 4)
-        return fail(LBM_E_UNSUPPORTED, "kernels implement Hermite orders up to 4");
+    if (p.hermite_order > 5)
+        return fail(LBM_E_UNSUPPORTED, "kernels implement Hermite orders up to 5");
     if (!(p.kn > 0)) return fail(LBM_E_INVALID, "kn must be positive");
     if (p.g_set && (p.g[1] != 0.0 || (p.dim == 3 && p.g[2] != 0.0)))
         return fail(LBM_E_INVALID, "the body force must be parallel to the walls (g.n = 0)");

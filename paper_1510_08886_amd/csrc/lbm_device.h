@@ -230,7 +230,7 @@ __device__ __forceinline__ void encode_all(const typename St<S>::R (&d)[SET::V],
     });
 }
 
-// f^(0) - w rho0 = w [ (rho - rho0) + rho sum_{n>=1} P_n / n! ] with the scalar
+// f^(0) - w rho0 = w [ (rho - rho0) + rho sum_{1<=n<=5} P_n / n! ] with the scalar
 // Hermite recurrence P_{n+1} = (u.xi) P_n - n |u|^2 P_{n-1} (u^n : H^(n)(xi)).
 template <class SET, typename R>
 __device__ __forceinline__ void equilibrium_dev(const PairTable<R> &t, const StepScalars<R> &s,
@@ -246,7 +246,7 @@ __device__ __forceinline__ void equilibrium_dev(const PairTable<R> &t, const Ste
         constexpr int p = decltype(pc)::value;
         const R ue = c * (R(SET::EX[p]) * ux + R(SET::EY[p]) * uy + R(SET::EZ[p]) * uz);
         R Pm = 1, P = ue, even = 0, odd = ue;
-        for (int k = 1; k < 4; ++k) {
+        for (int k = 1; k < 5; ++k) {
             const R Pn = ue * P - R(k) * u2 * Pm;
             Pm = P;
             P = Pn;

@@ -132,7 +132,7 @@ enum StepKind : int { kPingPong = 0, kGatherScatter = 1, kNodeLocal = 2 };
 // register load pipeline (occupancy 2), a persistent grid streaming the next
 // tile's gather into LDS with global_load_lds (LDS-limited to 8 waves per CU),
 // 64-, 128- and 512-node tiles, register caps for 6 to 8 waves per SIMD.
-template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND>
+template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND, bool N5>
 __global__ __launch_bounds__(256)
 void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
               uint32_t step) {
@@ -153,7 +153,7 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     }
     R d[SET::V];
     complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
-    relax2d<SET, R>(d, t, s, t.c);
+    relax2d<SET, R, N5>(d, t, s, t.c);
     T v[SET::V];
     encode_all<SET, S, true>(d, t, n, step, v);
     if constexpr (KIND == kGatherScatter) {
@@ -310,16 +310,26 @@ __global__ __launch_bounds__(256) void k_export2d(const void *pop, int layout, d
 template <class SET, Storage S>
 struct L2 {
     using R = typename St<S>::R;
-    template <int KIND>
-    static void launch_step(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
+    template <int KIND, bool N5>
+    static void launch_kind(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
                             hipStream_t st, uint32_t stp) {
         const dim3 g(blocks_for(s.nodes)), bl(256);
         if (s.aligned_rows && s.stream_stores)
-            hipLaunchKernelGGL((k_step2d<SET, S, true, true, KIND>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step2d<SET, S, true, true, KIND, N5>), g, bl, 0, st, b, t, s, stp);
         else if (s.aligned_rows)
-            hipLaunchKernelGGL((k_step2d<SET, S, true, false, KIND>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step2d<SET, S, true, false, KIND, N5>), g, bl, 0, st, b, t, s, stp);
         else
-            hipLaunchKernelGGL((k_step2d<SET, S, false, false, KIND>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step2d<SET, S, false, false, KIND, N5>), g, bl, 0, st, b, t, s,
+                               stp);
+    }
+    // Hermite order 5 (cn[5] != 0) is compiled for sets of quadrature order 9
+    template <int KIND>
+    static void launch_step(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
+                            hipStream_t st, uint32_t stp) {
+        if constexpr (SET::Q >= 9) {
+            if (s.cn[5] != R(0)) return launch_kind<KIND, true>(b, t, s, st, stp);
+        }
+        launch_kind<KIND, false>(b, t, s, st, stp);
     }
     static int step(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
                     uint32_t stp) {

@@ -51,14 +51,17 @@ __device__ __forceinline__ Moments2D<R> moments2d(const R (&d)[SET::V], const St
 // Hermite sums regrouped as polynomials in the integer velocity e, whose
 // coefficients are formed once per node (ue = u.xi, u2 = |u|^2, xi = c e):
 //   f^(0)/w  = drho + rho [1 + ue + (ue^2 - u2)/2 + (ue^3 - 3 u2 ue)/6
-//                          + (ue^4 - 6 u2 ue^2 + 3 u2^2)/24]   (terms up to N)
+//                          + (ue^4 - 6 u2 ue^2 + 3 u2^2)/24
+//                          + (ue^5 - 10 u2 ue^3 + 15 u2^2 ue)/120]   (terms up to N)
 //   tau F/w  = tau rho [(g.xi) + (g.xi)(u.xi) - g.u]
 //              + tau/2 (g.xi)(a2 : xi xi - tr a2) - tau (a2 g).xi  (Eq. nm.4)
 // so that, with g along x,
 //   even(e) = C0 + ue^2 (C2 + C4 ue^2) + e_x T ue
-//   odd(e)  = ue (R1 + rc3 ue^2) + e.L + e_x (e_x^2 Kxx + e_y^2 Kyy + e_x e_y Kxy)
+//   odd(e)  = ue (R1 + ue^2 (R3 + rc5 ue^2)) + e.L + e_x (e_x^2 Kxx + e_y^2 Kyy + e_x e_y Kxy)
 // and fbar* = fbar + omega (w (even +- odd) - fbar) (Eq. nm.8) on deviations.
-template <class SET, typename R>
+// N5 compiles the fifth-order term (Hermite order 5, sets of quadrature order
+// 9); without it rc5 = 0 and odd = ue (R1 + rc3 ue^2).
+template <class SET, typename R, bool N5 = false>
 __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
                                         const StepScalars<R> &s, R c) {
     constexpr int NR = SET::NR;
@@ -85,7 +88,9 @@ __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
     const R C4 = rc4;
     const R T = tr * gxc;
     // odd part
-    const R R1 = fma(R(-3) * rc3, u2, rho);
+    const R rc5 = N5 ? rho * s.cn[5] : R(0);
+    const R R1 = N5 ? fma(R(15) * rc5 * u2, u2, fma(R(-3) * rc3, u2, rho)) : fma(R(-3) * rc3, u2, rho);
+    const R R3 = N5 ? fma(R(-10) * rc5, u2, rc3) : rc3;
     const R hgt = R(0.5) * s.tau * gxc;
     const R Lx = fma(gxc, fma(R(-0.5) * s.tau, tra2, tr), -s.tau * a2xx * gxc);
     const R Ly = -s.tau * a2xy * gxc;
@@ -102,7 +107,11 @@ __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
         f = addk<ex * ex * ex>(f, Kxx);
         f = addk<ex * ey * ey>(f, Kyy);
         f = addk<ex * ex * ey>(f, Kxy);
-        const R odd = fma(ue, fma(rc3, ue2, R1), f);
+        R odd;
+        if constexpr (N5)
+            odd = fma(ue, fma(ue2, fma(rc5, ue2, R3), R1), f);
+        else
+            odd = fma(ue, fma(R3, ue2, R1), f);
         const R w = t.w[p];
         R &dp = d[NR + 2 * p];
         R &dm = d[NR + 2 * p + 1];
