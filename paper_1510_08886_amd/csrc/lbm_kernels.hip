@@ -138,10 +138,20 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
               uint32_t step) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
-    if (n >= (uint32_t)s.nodes) return;
-    const int j = (int)(n / (uint32_t)s.nx);
-    const int i = (int)(n - (uint32_t)j * s.nx);
+    // ALIGNED: a 2D grid of (x tile, row) blocks, so the row, and every row
+    // offset, is uniform (scalar registers); otherwise 256 consecutive nodes
+    int i, j;
+    uint32_t n;
+    if constexpr (ALIGNED) {
+        j = (int)blockIdx.y;
+        i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+        n = (uint32_t)j * (uint32_t)s.nx + (uint32_t)i;
+    } else {
+        n = blockIdx.x * 256u + threadIdx.x;
+        if (n >= (uint32_t)s.nodes) return;
+        j = (int)(n / (uint32_t)s.nx);
+        i = (int)(n - (uint32_t)j * s.nx);
+    }
     T *A = (T *)b.pop;
     const uint32_t own = aos_base<SET::V>(n);
     T raw[SET::V];
@@ -314,10 +324,14 @@ struct L2 {
     static void launch_kind(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
                             hipStream_t st, uint32_t stp) {
         const dim3 g(blocks_for(s.nodes)), bl(256);
+        // aligned rows: blocks of up to 256 nodes of one row (nx % 64 == 0)
+        const unsigned tb = s.nx % 256 == 0 ? 256u : (s.nx % 128 == 0 ? 128u : 64u);
+        const dim3 g2((unsigned)s.nx / tb, (unsigned)s.ny), bl2(tb);
         if (s.aligned_rows && s.stream_stores)
-            hipLaunchKernelGGL((k_step2d<SET, S, true, true, KIND, N5>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step2d<SET, S, true, true, KIND, N5>), g2, bl2, 0, st, b, t, s, stp);
         else if (s.aligned_rows)
-            hipLaunchKernelGGL((k_step2d<SET, S, true, false, KIND, N5>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step2d<SET, S, true, false, KIND, N5>), g2, bl2, 0, st, b, t, s,
+                               stp);
         else
             hipLaunchKernelGGL((k_step2d<SET, S, false, false, KIND, N5>), g, bl, 0, st, b, t, s,
                                stp);

@@ -345,10 +345,21 @@ void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
               uint32_t step) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
-    const uint32_t n = blockIdx.x * 256u + threadIdx.x;
-    if (n >= (uint32_t)s.nodes) return;
+    // ALIGNED: a 2D grid of (x tile, row) blocks with row = k * ny + j, so j,
+    // k and every row offset are uniform (scalar registers)
     int i, j, k;
-    node_ijk(n, s.nx, s.ny, i, j, k);
+    uint32_t n;
+    if constexpr (ALIGNED) {
+        const uint32_t row = blockIdx.y;
+        k = (int)(row / (uint32_t)s.ny);
+        j = (int)(row - (uint32_t)k * (uint32_t)s.ny);
+        i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+        n = row * (uint32_t)s.nx + (uint32_t)i;
+    } else {
+        n = blockIdx.x * 256u + threadIdx.x;
+        if (n >= (uint32_t)s.nodes) return;
+        node_ijk(n, s.nx, s.ny, i, j, k);
+    }
     T *A = (T *)b.pop;
     const uint32_t own = aos_base<SET::V>(n);
     T raw[SET::V];
@@ -516,10 +527,13 @@ struct L3 {
     static void launch_step(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
                             hipStream_t st, uint32_t stp) {
         const dim3 g(blocks_for(s.nodes)), bl(256);
+        // aligned rows: blocks of up to 256 nodes of one row (nx % 64 == 0)
+        const unsigned tb = s.nx % 256 == 0 ? 256u : (s.nx % 128 == 0 ? 128u : 64u);
+        const dim3 g2((unsigned)s.nx / tb, (unsigned)(s.ny * s.nz)), bl2(tb);
         if (s.aligned_rows && s.stream_stores)
-            hipLaunchKernelGGL((k_step3d<SET, S, true, true, KIND>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step3d<SET, S, true, true, KIND>), g2, bl2, 0, st, b, t, s, stp);
         else if (s.aligned_rows)
-            hipLaunchKernelGGL((k_step3d<SET, S, true, false, KIND>), g, bl, 0, st, b, t, s, stp);
+            hipLaunchKernelGGL((k_step3d<SET, S, true, false, KIND>), g2, bl2, 0, st, b, t, s, stp);
         else
             hipLaunchKernelGGL((k_step3d<SET, S, false, false, KIND>), g, bl, 0, st, b, t, s, stp);
     }
