@@ -250,7 +250,11 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->halo = d.halo;
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
-    s->aligned_rows = (p.nx % 64) == 0;
+    // aligned rows: whole 64-node blocks per row; the aligned kernels address a
+    // population array of below 2 GiB with 32-bit buffer offsets
+    s->aligned_rows = (p.nx % 64) == 0 &&
+                      (double)d.V * (double)s->nodes * (double)storage_bytes(p.storage) <
+                          (double)(1u << 31);
     s->stream_stores = 2.0 * (double)d.V * (double)s->plane * (double)storage_bytes(p.storage) >
                        (double)(1u << 30);
 }

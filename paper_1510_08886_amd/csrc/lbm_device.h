@@ -298,27 +298,114 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *partial) 
 }
 
 // ---------------------------------------------------------------------------
+// raw buffer accesses: a scalar descriptor (base, size in bytes), a per-lane
+// 32-bit byte offset and a uniform (scalar) byte offset. Used by the aligned
+// step kernels, whose row offsets are uniform, so that an access costs no
+// vector address arithmetic. Word 3 of the descriptor selects the 32-bit data
+// format of the gfx9 family; accesses beyond `bytes` read 0 and drop stores.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+
+// STREAM: non-temporal hint (cache policy bit 1)
+template <bool STREAM, typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, T v, uint32_t voff,
+                                          uint32_t soff) {
+    constexpr int aux = STREAM ? 2 : 0;
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, aux);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff,
+                                              aux);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff,
+                                              aux);
+}
+
+// ---------------------------------------------------------------------------
 // node-local accesses of the in-place population array (PopLayout), shared by
 // the 2D and 3D kernels
 // ---------------------------------------------------------------------------
-// STREAMED -> pre-collision values: slot alpha of the node itself
+// Element position split into a per-lane part l, a uniform part u and a slot
+// offset o (a compile-time constant once inlined): the flat index is
+// l + u + o. Aligned step kernels keep row offsets in u (scalar registers) and
+// the column part in l.
+struct Ix {
+    uint32_t l, u, o;
+};
+__device__ __forceinline__ Ix slot_of(Ix x, int a) { return {x.l, x.u, x.o + 64u * (uint32_t)a}; }
+
+// flat pointer access
+template <typename T>
+struct GlobalPop {
+    T *A;
+    __device__ __forceinline__ T ld(Ix x) const { return A[(x.u + x.l) + x.o]; }
+    template <bool STREAM>
+    __device__ __forceinline__ void st(Ix x, T v) const {
+        store_pop<STREAM>(A + (x.u + x.l) + x.o, v);
+    }
+    // a position as one flat index (in l)
+    static __device__ __forceinline__ Ix flat(Ix x) { return {(x.u + x.l) + x.o, 0u, 0u}; }
+};
+
+// raw buffer access (arrays below 2 GiB): the uniform part becomes the scalar
+// offset operand
+template <typename T>
+struct BufferPop {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BufferPop(const void *p, uint32_t bytes) : r(make_rsrc(p, bytes)) {}
+    __device__ __forceinline__ T ld(Ix x) const {
+        return buf_load<T>(r, x.l * (uint32_t)sizeof(T), (x.u + x.o) * (uint32_t)sizeof(T));
+    }
+    template <bool STREAM>
+    __device__ __forceinline__ void st(Ix x, T v) const {
+        buf_store<STREAM>(r, v, x.l * (uint32_t)sizeof(T), (x.u + x.o) * (uint32_t)sizeof(T));
+    }
+    // the slot offset folded into the uniform part
+    static __device__ __forceinline__ Ix flat(Ix x) { return {x.l, x.u + x.o, 0u}; }
+};
+
+// kStreamed -> pre-collision values: slot alpha of the node itself
+template <class SET, class P, typename T>
+__device__ __forceinline__ void read_local(const P &pop, Ix own, T (&raw)[SET::V]) {
+#pragma unroll
+    for (int a = 0; a < SET::V; ++a) raw[a] = pop.ld(slot_of(own, a));
+}
+
 template <class SET, typename T>
 __device__ __forceinline__ void read_local(const T *A, uint32_t own, T (&raw)[SET::V]) {
-#pragma unroll
-    for (int a = 0; a < SET::V; ++a) raw[a] = A[own + 64 * a];
+    read_local<SET>(GlobalPop<T>{const_cast<T *>(A)}, Ix{own, 0u, 0u}, raw);
 }
 
 // post-collision values -> the node's own slots: kLocal (SWAP, velocity alpha
 // in the slot of -alpha) or kDirect (slot alpha)
-template <class SET, bool SWAP, bool STREAM, typename T>
-__device__ __forceinline__ void write_own(T *A, uint32_t own, const T (&v)[SET::V]) {
+template <class SET, bool SWAP, bool STREAM, class P, typename T>
+__device__ __forceinline__ void write_own(const P &pop, Ix own, const T (&v)[SET::V]) {
     constexpr int NR = SET::NR;
-    if constexpr (NR) store_pop<STREAM>(A + own, v[0]);
+    if constexpr (NR) pop.template st<STREAM>(own, v[0]);
     for_pairs<SET::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        store_pop<STREAM>(A + own + 64 * (SWAP ? NR + 2 * p + 1 : NR + 2 * p), v[NR + 2 * p]);
-        store_pop<STREAM>(A + own + 64 * (SWAP ? NR + 2 * p : NR + 2 * p + 1), v[NR + 2 * p + 1]);
+        pop.template st<STREAM>(slot_of(own, SWAP ? NR + 2 * p + 1 : NR + 2 * p), v[NR + 2 * p]);
+        pop.template st<STREAM>(slot_of(own, SWAP ? NR + 2 * p : NR + 2 * p + 1), v[NR + 2 * p + 1]);
     });
+}
+
+template <class SET, bool SWAP, bool STREAM, typename T>
+__device__ __forceinline__ void write_own(T *A, uint32_t own, const T (&v)[SET::V]) {
+    write_own<SET, SWAP, STREAM>(GlobalPop<T>{A}, Ix{own, 0u, 0u}, v);
 }
 
 // ---------------------------------------------------------------------------

@@ -81,6 +81,21 @@ def test_duct_low_precision_storage(storage, tol_mdot, tol_pop):
     assert np.max(np.abs(pg - po) / w) <= tol_pop
 
 
+@pytest.mark.parametrize("storage,tol_pop", [("f32", 1e-7), ("f16dev", 1e-3)])
+def test_duct_aligned_rows_in_place(storage, tol_pop):
+    """nx = 64: the row-grid kernels (buffer addressing in 16-bit storage), both
+    in-place kinds, element by element against the oracle."""
+    nx, ny, nz = 64, 12, 10
+    rho, u = wl.random_state(nx * ny * nz, 3, seed=23, amp=1e-3)
+    d, g, o = make_pair("D3V39", 3, nx, ny, nz, kn=0.1, storage=storage, rho=rho, u=u)
+    w = d.weights[:, None, None, None]
+    for steps in (1, 30):
+        g.run(steps)
+        o.run(steps, nthreads=16)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po) / w) <= tol_pop, steps
+
+
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16dev", 1e-3)])
 def test_full_size_duct_against_streamwise_invariant_oracle(storage, tol):
     from paper_1510_08886_amd import lbm

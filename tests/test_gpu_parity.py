@@ -83,6 +83,24 @@ def test_low_precision_storage(storage, tol_mdot, tol_pop):
     assert np.max(np.abs(pg - po) / w) <= tol_pop
 
 
+@pytest.mark.parametrize("storage,tol_mdot,tol_pop", [("f32", 1e-5, 1e-8), ("f16dev", 1e-3, 1e-4)])
+def test_aligned_rows_in_place(storage, tol_mdot, tol_pop):
+    """Rows of whole 64-node blocks (nx = 128) take the row-grid kernels, in
+    16-bit storage with buffer addressing: both in-place kinds (odd and even
+    step counts) element by element against the oracle."""
+    nx, ny = 128, 20
+    rho, u = wl.random_state(nx * ny, 2, seed=21, amp=1e-3)
+    d, g, o = make_pair("D2V37", 4, nx, ny, kn=0.05, storage=storage, rho=rho, u=u)
+    w = d.weights[:, None, None]
+    for steps in (1, 40, 59):
+        g.run(steps)
+        o.run(steps)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po) / w) <= tol_pop, steps
+    og, oo = g.observe(), o.observe()
+    assert abs(og["mdot"] - oo["mdot"]) <= tol_mdot * abs(oo["mdot"])
+
+
 def test_full_size_throughput_channel_one_step_and_mass():
     """2048 x 512 FP32 D2V37 with the seeded density field: one step against the
     oracle over the whole grid, then 1000 steps conserve mass to FP32 rounding."""
