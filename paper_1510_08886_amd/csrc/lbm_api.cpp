@@ -250,11 +250,12 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->halo = d.halo;
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
-    // aligned rows: whole 64-node blocks per row; the aligned kernels address a
-    // population array of below 2 GiB with 32-bit buffer offsets
+    // aligned rows: whole 64-node blocks per row; in 16-bit storage the
+    // aligned kernels address a population copy with 32-bit buffer offsets,
+    // so it must stay below 2 GiB
     s->aligned_rows = (p.nx % 64) == 0 &&
-                      (double)d.V * (double)s->nodes * (double)storage_bytes(p.storage) <
-                          (double)(1u << 31);
+                      (storage_bytes(p.storage) != 2 ||
+                       (double)d.V * (double)s->nodes * 2.0 < (double)(1u << 31));
     s->stream_stores = 2.0 * (double)d.V * (double)s->plane * (double)storage_bytes(p.storage) >
                        (double)(1u << 30);
 }
