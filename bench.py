@@ -26,21 +26,22 @@ import lbm_workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_step_d2v37_f32_2048x512.json"
-# what the headline kernels' traffic depends on: their sources, the build flags
-# and the host's choice between in-place and ping-pong stepping
+# what the headline kernels' traffic depends on: their sources, the device
+# compiler flags and the host's choice between in-place and ping-pong stepping
 KERNEL_SOURCES = ["paper_1510_08886_amd/csrc/lbm_kernels.hip",
                   "paper_1510_08886_amd/csrc/lbm_device.h",
                   "paper_1510_08886_amd/csrc/lbm_node2d.h",
                   "paper_1510_08886_amd/csrc/lbm_internal.h",
                   "paper_1510_08886_amd/csrc/lbm_sets.h",
-                  "paper_1510_08886_amd/csrc/lbm_api.cpp",
-                  "paper_1510_08886_amd/build.py"]
+                  "paper_1510_08886_amd/csrc/lbm_api.cpp"]
 
 
 def kernel_hash() -> str:
+    from paper_1510_08886_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
         h.update((ROOT / s).read_bytes())
+    h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
@@ -82,6 +83,35 @@ def cpu_baseline(budget_s: float = 20.0):
             "kind": "oracle",
             "sample": f"{steps} steps of the full 2048x512 D2V37 grid in FP64 "
                       f"(after 1 warm-up step), {el:.1f} s"}
+
+
+def copy_gbs(nbytes: int, reps: int = 10) -> float:
+    """Bandwidth of the library's plain streaming copy (one 16-byte vector per
+    thread, non-temporal stores) of nbytes each way, alternating direction
+    between two buffers so that every copy reads what the previous one wrote
+    (as a step does): the practical ceiling a streaming kernel of the same
+    footprint reaches on this part, next to the 8 TB/s peak."""
+    import torch
+
+    from paper_1510_08886_amd import lbm
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for k in range(4):
+        lbm.stream_copy(*((a, b) if k % 2 == 0 else (b, a)), st)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for k in range(reps):
+        lbm.stream_copy(*((a, b) if k % 2 == 0 else (b, a)), st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
 
 
 def _oracle_mdot(name, ny, kn, steps):
@@ -199,6 +229,7 @@ def duct_block():
     nodes = c["nx"] * c["ny"] * c["nz"]
     out = {"workload": "D3V39 N=3 square duct 128x256x256, Kn=0.1, Ma=1e-3, from rest, "
                        f"{c['steps']} steps", "oracle_mdot": want}
+    copy = {size: copy_gbs(d.V * size * nodes) for size in (4, 2)}
     for storage, size in (("f32", 4), ("f16dev", 2)):
         prob = lbm.Problem(dim=3, nx=c["nx"], ny=c["ny"], nz=c["nz"], kn=c["kn"], ma=c["ma"],
                            hermite_order=c["N"], storage=storage)
@@ -217,6 +248,8 @@ def duct_block():
         out[storage] = {"mlups": round(nodes * c["steps"] / (ms * 1e-3) / 1e6, 1),
                         "ms_per_step": ms / c["steps"],
                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "copy_gbs": round(copy[size], 1),
+                        "frac_of_copy": round(gbs / copy[size], 4),
                         "mdot": ob["mdot"],
                         "mdot_rel_err_vs_oracle": abs(ob["mdot"] - want) / abs(want),
                         "mass_drift": abs(ob["mass"] - m0) / m0}
@@ -349,6 +382,10 @@ def main():
         "mdot_after": obs["mdot"],
     }
     s.close()
+    cg = copy_gbs(bytes_per_launch // 2)
+    out["measured_copy"] = {"bytes_each_way": bytes_per_launch // 2, "gbs": round(cg, 1),
+                            "step_frac_of_copy": round(achieved / cg, 4),
+                            "note": "plain streaming copy of one population array (lbm_stream_copy)"}
     if not args.no_batch:
         out["batched"] = batched_block()
     if not args.no_serve:

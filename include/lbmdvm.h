@@ -299,6 +299,17 @@ int lbm_batch_autotune(lbm_batch_t *b, int trial_steps, int *threads_out);
 
 int lbm_batch_stats(const lbm_batch_t *b, lbm_batch_stats_t *out);
 
+/* ---- measurement aid (not part of the method) ------------------------------ */
+
+/* Plain streaming copy of `bytes` from src to dst (device buffers, 16-byte
+ * aligned, not overlapping; bytes a multiple of 16), asynchronous on `stream`
+ * (a hipStream_t; NULL = the default stream): each byte read once and written
+ * once, one 16-byte vector per thread, non-temporal stores. Its bandwidth is
+ * the practical ceiling the HBM-bound step kernels are compared with, next to
+ * the part's peak.
+ * LBM_E_INVALID on a bad argument, LBM_E_DEVICE if the launch fails. */
+int lbm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,7 @@ SIGNATURES = {
     "lbm_batch_tune": ([_P, _I, _I], _I),
     "lbm_batch_autotune": ([_P, _I, _IP], _I),
     "lbm_batch_stats": ([_P, ctypes.POINTER(BatchStatsC)], _I),
+    "lbm_stream_copy": ([_P, _P, ctypes.c_size_t, _P], _I),
 }
 
 
@@ -163,6 +164,21 @@ def profile_analysis(u) -> dict:
           "lbm_profile_analysis")
     return dict(u_center=st.u_center, u_wall=st.u_wall, slip=st.slip, mean=st.mean, u_ns=ns,
                 u_neq=neq)
+
+
+def stream_copy(src, dst, stream=None):
+    """Plain streaming copy between two equally sized contiguous device
+    tensors (a bandwidth reference, not part of the method), asynchronous on
+    `stream` (default: torch's current stream)."""
+    import torch
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("src and dst differ in size")
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("need contiguous device tensors")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    check(lib().lbm_stream_copy(_P(src.data_ptr()), _P(dst.data_ptr()),
+                                src.numel() * src.element_size(), _P(st.cuda_stream)),
+          "lbm_stream_copy")
 
 
 class Dvm:

@@ -128,3 +128,11 @@ def test_state_bytes_in_place_up_to_512_mib_then_two_copies():
     pop4, _ = lbm.state_bytes(d3, lbm.Problem(dim=3, nx=64, ny=160, nz=160, kn=0.1,
                                               hermite_order=3, storage="f64"))
     assert pop4 == 39 * 64 * 160 * 160 * 8 and pop4 <= 512 << 20
+
+
+def test_stream_copy_rejects_bad_arguments_without_a_launch():
+    so = lbm.lib()
+    assert so.lbm_stream_copy(None, None, 16, None) == -1
+    # 16-byte alignment and size (checked before any device call)
+    assert so.lbm_stream_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), 24, None) == -1
+    assert so.lbm_stream_copy(ctypes.c_void_p(8), ctypes.c_void_p(32), 32, None) == -1
