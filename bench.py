@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 from pathlib import Path
@@ -36,11 +37,20 @@ KERNEL_SOURCES = ["paper_1510_08886_amd/csrc/lbm_kernels.hip",
                   "paper_1510_08886_amd/csrc/lbm_api.cpp"]
 
 
+_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def _code_only(src: str) -> str:
+    """C/C++ source without comments, whitespace runs collapsed."""
+    src = _TOKENS.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", src)
+    return " ".join(src.split())
+
+
 def kernel_hash() -> str:
     from paper_1510_08886_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
-        h.update((ROOT / s).read_bytes())
+        h.update(_code_only((ROOT / s).read_text()).encode())
     h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 

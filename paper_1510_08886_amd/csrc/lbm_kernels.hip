@@ -125,8 +125,9 @@ __device__ __forceinline__ void write_gs(const P &pop, const NB &nb, Ix own, int
 // node-local -> kLocal).
 enum StepKind : int { kPingPong = 0, kGatherScatter = 1, kNodeLocal = 2 };
 
-// One block of 256 threads per tile of 256 consecutive nodes. Each thread
-// issues all its loads before it decodes any, so a wavefront has its whole
+// One thread per node, blocks of up to 256 threads: one block per (x tile,
+// row) when rows are whole 64-node blocks, else per 256 consecutive nodes.
+// Each thread issues all its loads before it decodes any, so a wavefront has its whole
 // gather in flight at once; wall slots are patched after the loads. The host
 // runs arrays of up to 512 MiB in place (on MI355X ~7% faster than ping-pong
 // for the 155 MB D2V37 channel: the array stays largely in the 256 MB
@@ -159,7 +160,8 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     // slot offsets in the scalar operand (arrays below 2 GiB), which removes
     // the vector address arithmetic. Measured on MI355X: 4% faster for the
     // FP16 duct step, whose arithmetic outweighs its halved traffic; 0.4-2%
-    // slower for FP32 steps, which keep flat 64-bit addresses.
+    // slower for FP32 steps (the compiler then batches the stores after the
+    // collision instead of interleaving them), which keep flat addresses.
     constexpr bool BUF = ALIGNED && sizeof(T) == 2;
     T *A = (T *)b.pop;
     auto pop_at = [&](void *base) {

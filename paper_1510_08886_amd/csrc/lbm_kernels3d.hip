@@ -341,8 +341,9 @@ __device__ __forceinline__ void node_ijk(uint32_t n, int nx, int ny, int &i, int
 // gather/scatter (kLocal -> kStreamed) and node-local (kStreamed -> kLocal)
 enum StepKind3 : int { kPingPong3 = 0, kGatherScatter3 = 1, kNodeLocal3 = 2 };
 
-// One 256-thread block per 256 consecutive nodes. ALIGNED (nx a multiple of
-// 64) is compiled apart.
+// One thread per node, blocks of up to 256 threads: one block per (x tile,
+// row) when nx is a multiple of 64 (ALIGNED, compiled apart), else per 256
+// consecutive nodes.
 template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND>
 __global__ __launch_bounds__(256)
 void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
@@ -368,7 +369,8 @@ void k_step3d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     // slot offsets in the scalar operand (arrays below 2 GiB), which removes
     // the vector address arithmetic. Measured on MI355X: 4% faster for the
     // FP16 duct step, whose arithmetic outweighs its halved traffic; 0.4-2%
-    // slower for FP32 steps, which keep flat 64-bit addresses.
+    // slower for FP32 steps (the compiler then batches the stores after the
+    // collision instead of interleaving them), which keep flat addresses.
     constexpr bool BUF = ALIGNED && sizeof(T) == 2;
     T *A = (T *)b.pop;
     auto pop_at = [&](void *base) {
