@@ -328,3 +328,20 @@ def test_duct_golden_file_is_consistent():
     assert steps == list(range(50, 501, 50))
     assert all(abs(m - 65536.0) <= 1e-12 * 65536.0 for m in mass)
     assert all(b > a for a, b in zip(mdot, mdot[1:]))
+
+
+def test_sweep_golden_file_matches_recipe_and_oracle():
+    """The stored oracle mass flows of the sweep's smallest channels
+    (tests/golden/sweep_d2v37_mdot.txt) belong to the current sweep recipe, and
+    re-running the oracle on the two cheapest reproduces them."""
+    from pathlib import Path
+
+    from tests.golden import make_sweep_golden as msg
+    rows = [l.split() for l in (Path(__file__).resolve().parent / "golden" / "sweep_d2v37_mdot.txt")
+            .read_text().splitlines() if l and not l.startswith("#")]
+    assert [(int(r[0]), int(r[1]), float(r[2])) for r in rows] == msg.channels()
+    for r in rows[:2]:
+        o = stepper.OracleSolver(dvm.named_dvm("D2V37"), nx=1, ny=int(r[1]), kn=float(r[2]),
+                                 ma=1e-3, N=4).init()
+        o.run(int(r[3]))
+        assert abs(o.observe()["mdot"] - float(r[4])) <= 1e-14 * float(r[4])
