@@ -147,8 +147,17 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     int i, j;
     uint32_t n;
     if constexpr (ALIGNED) {
-        j = (int)blockIdx.y;
-        i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+        uint32_t bx = blockIdx.x, by = blockIdx.y;
+        if ((s.ny & 7) == 0) {
+            // Workgroups go to the 8 XCDs round-robin by linear id; give each
+            // XCD a band of whole rows, so the cache lines that two adjacent
+            // tiles of a row share (shifted runs) stay in one L2.
+            const uint32_t id = by * gridDim.x + bx, xcd = id & 7u, k = id >> 3;
+            by = xcd * ((uint32_t)s.ny >> 3) + k / gridDim.x;
+            bx = k % gridDim.x;
+        }
+        j = (int)by;
+        i = (int)(bx * blockDim.x + threadIdx.x);
         n = (uint32_t)j * (uint32_t)s.nx + (uint32_t)i;
     } else {
         n = blockIdx.x * 256u + threadIdx.x;
