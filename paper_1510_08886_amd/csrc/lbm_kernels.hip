@@ -147,17 +147,15 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     int i, j;
     uint32_t n;
     if constexpr (ALIGNED) {
-        uint32_t bx = blockIdx.x, by = blockIdx.y;
-        if ((s.ny & 7) == 0) {
-            // Workgroups go to the 8 XCDs round-robin by linear id; give each
-            // XCD a band of whole rows, so the cache lines that two adjacent
-            // tiles of a row share (shifted runs) stay in one L2.
-            const uint32_t id = by * gridDim.x + bx, xcd = id & 7u, k = id >> 3;
-            by = xcd * ((uint32_t)s.ny >> 3) + k / gridDim.x;
-            bx = k % gridDim.x;
-        }
-        j = (int)by;
-        i = (int)(bx * blockDim.x + threadIdx.x);
+        // Workgroups go to the 8 XCDs round-robin by linear id. XCD x takes
+        // the k-th of its workgroups from a contiguous band of tiles in row
+        // order (x * (total / 8) + min(x, total % 8) + k), so the cache lines
+        // two adjacent tiles of a row share (shifted runs) stay in one L2.
+        const uint32_t tiles = gridDim.x, total = tiles * gridDim.y;
+        const uint32_t id = blockIdx.y * tiles + blockIdx.x, xcd = id & 7u;
+        const uint32_t lin = xcd * (total >> 3) + min(xcd, total & 7u) + (id >> 3);
+        j = (int)(lin / tiles);
+        i = (int)((lin - (uint32_t)j * tiles) * blockDim.x + threadIdx.x);
         n = (uint32_t)j * (uint32_t)s.nx + (uint32_t)i;
     } else {
         n = blockIdx.x * 256u + threadIdx.x;

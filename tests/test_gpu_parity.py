@@ -83,13 +83,15 @@ def test_low_precision_storage(storage, tol_mdot, tol_pop):
     assert np.max(np.abs(pg - po) / w) <= tol_pop
 
 
+@pytest.mark.parametrize("nx,ny", [(128, 20), (512, 13), (192, 11)])
 @pytest.mark.parametrize("storage,tol_mdot,tol_pop", [("f32", 1e-5, 1e-8), ("f16dev", 1e-3, 1e-4)])
-def test_aligned_rows_in_place(storage, tol_mdot, tol_pop):
-    """Rows of whole 64-node blocks (nx = 128) take the row-grid kernels, in
-    16-bit storage with buffer addressing: both in-place kinds (odd and even
-    step counts) element by element against the oracle."""
-    nx, ny = 128, 20
-    rho, u = wl.random_state(nx * ny, 2, seed=21, amp=1e-3)
+def test_aligned_rows_in_place(storage, tol_mdot, tol_pop, nx, ny):
+    """Rows of whole 64-node blocks take the row-grid kernels (tiles of 128,
+    256 and 64 nodes; 1, 2 and 3 tiles per row; the per-XCD tile bands end
+    mid-row when the tile count is not a multiple of 8), in 16-bit storage with
+    buffer addressing: both in-place kinds (odd and even step counts) element
+    by element against the oracle."""
+    rho, u = wl.random_state(nx * ny, 2, seed=21 + nx + ny, amp=1e-3)
     d, g, o = make_pair("D2V37", 4, nx, ny, kn=0.05, storage=storage, rho=rho, u=u)
     w = d.weights[:, None, None]
     for steps in (1, 40, 59):
