@@ -227,6 +227,44 @@ def serving_block(n_plain: int):
     }
 
 
+def channel_block():
+    """The FP64 D2V17 channel, nx = 1, ny = 40, Kn = 0.1, 20000 steps from rest:
+    launch-bound, so the figure is the time to solution; mass flow and profile
+    against the stored FP64 oracle run of the same channel."""
+    import numpy as np
+    import torch
+
+    from paper_1510_08886_amd import lbm
+
+    c = wl.CHANNEL_D2V17
+    rows = [l.split() for l in (ROOT / "tests" / "golden" / "channel_d2v17.txt").read_text()
+            .splitlines() if l and not l.startswith("#")]
+    gold = {r[0]: float(r[1]) for r in rows if r[0] != "ux"}
+    ux_gold = np.array([float(r[2]) for r in rows if r[0] == "ux"])
+    d = lbm.Dvm.named(c["dvm"])
+    prob = lbm.Problem(dim=2, nx=c["nx"], ny=c["ny"], kn=c["kn"], ma=c["ma"], hermite_order=c["N"],
+                       storage=c["storage"])
+    s = lbm.Solver(d, prob, device="cuda:0").init()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.run(c["steps"])
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ob = s.observe()
+    ux = ob["u"][:, 0, 0].cpu().numpy()
+    s.close()
+    return {"workload": "D2V17 N=3 FP64 channel 1x40, Kn=0.1, Ma=1e-3, from rest, "
+                        f"{c['steps']} steps",
+            "time_to_solution_s": round(ms * 1e-3, 4),
+            "us_per_step": round(ms * 1e3 / c["steps"], 2),
+            "mdot": ob["mdot"],
+            "mdot_rel_err_vs_oracle": abs(ob["mdot"] - gold["mdot"]) / abs(gold["mdot"]),
+            "u_max_rel_err_vs_oracle": float(np.max(np.abs(ux - ux_gold)) / np.max(np.abs(ux_gold)))}
+
+
 def duct_block():
     """3D square duct on D3V39, 128 x 256 x 256 (periodic x, diffuse Maxwell
     walls on the four y and z faces), Kn = 0.1, from rest, 500 steps with FP32
@@ -325,6 +363,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Kn sweep")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-duct", action="store_true", help="skip the 3D duct runs")
+    ap.add_argument("--no-channel", action="store_true", help="skip the FP64 D2V17 channel run")
     ap.add_argument("--no-scatter", action="store_true", help="skip the scattering-stencil runs")
     ap.add_argument("--plain-serve-requests", type=int, default=100,
                     help="prefix of the serving trace run by the one-at-a-time plain baseline")
@@ -409,6 +448,8 @@ def main():
         out["batched"] = batched_block()
     if not args.no_serve:
         out["serving"] = serving_block(args.plain_serve_requests)
+    if not args.no_channel:
+        out["channel_d2v17_f64"] = channel_block()
     if not args.no_duct:
         out["duct"] = duct_block()
     if not args.no_scatter:

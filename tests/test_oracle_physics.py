@@ -345,3 +345,24 @@ def test_sweep_golden_file_matches_recipe_and_oracle():
                                  ma=1e-3, N=4).init()
         o.run(int(r[3]))
         assert abs(o.observe()["mdot"] - float(r[4])) <= 1e-14 * float(r[4])
+
+
+def test_channel_golden_file_matches_oracle():
+    """The stored 20000-step D2V17 channel (tests/golden/channel_d2v17.txt):
+    mirror-symmetric profile, mass rho0 * ny, and a re-run of the oracle
+    reproduces it."""
+    from pathlib import Path
+    rows = [l.split() for l in (Path(__file__).resolve().parent / "golden" / "channel_d2v17.txt")
+            .read_text().splitlines() if l and not l.startswith("#")]
+    kv = {r[0]: float(r[1]) for r in rows if r[0] != "ux"}
+    ux = np.array([float(r[2]) for r in rows if r[0] == "ux"])
+    assert len(ux) == 40 and kv["steps"] == 20000
+    # mirror nodes sum their populations in different orders: rounding at the
+    # scale of the populations (~1), not of u (~1e-3)
+    assert np.max(np.abs(ux - ux[::-1])) <= 1e-15
+    assert abs(kv["mass"] - 40.0) <= 1e-13 * 40.0
+    o = stepper.OracleSolver(dvm.named_dvm("D2V17"), nx=1, ny=40, kn=0.1, ma=1e-3, N=3).init()
+    o.run(20000)
+    ob = o.observe()
+    assert abs(ob["mdot"] - kv["mdot"]) <= 1e-14 * kv["mdot"]
+    assert np.max(np.abs(ob["u"][:, 0, 0] - ux)) <= 1e-14 * np.max(ux)
