@@ -385,11 +385,6 @@ __device__ __forceinline__ void read_local(const P &pop, Ix own, T (&raw)[SET::V
     for (int a = 0; a < SET::V; ++a) raw[a] = pop.ld(slot_of(own, a));
 }
 
-template <class SET, typename T>
-__device__ __forceinline__ void read_local(const T *A, uint32_t own, T (&raw)[SET::V]) {
-    read_local<SET>(GlobalPop<T>{const_cast<T *>(A)}, Ix{own, 0u, 0u}, raw);
-}
-
 // post-collision values -> the node's own slots: kLocal (SWAP, velocity alpha
 // in the slot of -alpha) or kDirect (slot alpha)
 template <class SET, bool SWAP, bool STREAM, class P, typename T>
