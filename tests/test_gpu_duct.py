@@ -152,3 +152,28 @@ def test_f64_pingpong_path_elementwise():
         pg, po = populations_both(d, g, o)
         assert np.max(np.abs(pg - po)) <= 1e-14
     assert abs(g.observe()["mdot"] - o.observe()["mdot"]) <= 1e-12 * abs(o.observe()["mdot"])
+
+
+def test_full_size_scattering_duct_against_one_column_oracle():
+    """The D3V96 duct at its benchmark size, 128 x 256 x 256 FP32 (two 3.2 GB
+    copies, ping-pong, halo 7), 12 steps from rest: every x column identical,
+    mass kept, and the mass flow against the oracle's one-column run of the
+    same duct (exact by streamwise invariance of a start uniform in x)."""
+    from paper_1510_08886_amd import lbm
+    c = wl.SCATTER_D3V96
+    d = lbm.Dvm.named(c["dvm"])
+    prob = lbm.Problem(dim=3, nx=c["nx"], ny=c["ny"], nz=c["nz"], kn=c["kn"], ma=c["ma"],
+                       hermite_order=c["N"], storage="f32")
+    s = lbm.Solver(d, prob).init()
+    m0 = s.observe()["mass"]
+    s.run(12)
+    ob = s.observe()
+    ux = ob["u"][..., 0]
+    assert torch.equal(ux, ux[..., :1].expand_as(ux))
+    assert abs(ob["mass"] - m0) <= 1e-6 * m0
+    got = ob["mdot"]
+    s.close()
+    _, _, o = make_pair("D3V96", c["N"], 1, c["ny"], c["nz"], kn=c["kn"], ma=c["ma"])
+    o.run(12, nthreads=16)
+    want = o.observe()["mdot"]
+    assert abs(got - want) <= 1e-5 * abs(want), (got, want)

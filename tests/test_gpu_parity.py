@@ -187,3 +187,20 @@ def test_hermite_order_five(storage, tol_pop):
     assert np.max(err) <= tol_pop
     og, oo = g.observe(), o.observe()
     assert abs(og["mdot"] - oo["mdot"]) <= (1e-12 if storage == "f64" else 1e-5) * abs(oo["mdot"])
+
+
+def test_full_size_scattering_channel_one_step():
+    """The D2V32 channel at its benchmark size, 2048 x 512 FP32 (in place, halo
+    12, per-XCD tile bands), with the seeded density field: one step against
+    the oracle over the whole grid, then the second (gather/scatter) kind."""
+    c = wl.SCATTER_D2V32
+    rho = wl.density_field(c["ny"], c["nx"])
+    d, g, o = make_pair(c["dvm"], c["N"], c["nx"], c["ny"], kn=c["kn"], ma=c["ma"],
+                        storage="f32", rho=rho)
+    w = d.weights[:, None, None]
+    for _ in range(2):
+        g.run(1)
+        o.run(1, nthreads=min(16, os.cpu_count() or 1))
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po) / w) <= 1e-6
+    assert abs(g.observe()["mdot"] - o.observe()["mdot"]) <= 1e-5 * abs(o.observe()["mdot"])
