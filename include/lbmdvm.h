@@ -190,8 +190,22 @@ int lbm_solver_destroy(lbm_solver_t *s);
  * FP64 arrays in node order ((k * ny + j) * nx + i); NULL means rho0 and rest. */
 int lbm_init_equilibrium(lbm_solver_t *s, const double *rho_dev, const double *u_dev);
 
-/* Enqueue nsteps fused stream + wall + collide steps (Eq. nm.8); asynchronous. */
+/* Enqueue nsteps fused stream + wall + collide steps (Eq. nm.8); asynchronous.
+ * For small problems (see lbm_solver_set_graph_steps) runs of two or more
+ * steps are replayed from HIP graphs of up to 256 captured steps each, which
+ * the library instantiates and caches per solver (at most 8); the results are
+ * bit for bit those of one launch per step. */
 int lbm_run(lbm_solver_t *s, int64_t nsteps);
+
+/* Longest step sequence lbm_run replays from one captured HIP graph
+ * (0: one launch per step; at most 4096). The default is 256 for population
+ * copies up to 16 MiB, where launch latency dominates the step, and 0 above.
+ * LBM_E_UNSUPPORTED for a non-zero value in FP16-deviation storage, whose
+ * stochastic rounding keys on the step counter (a replay repeats its launch
+ * arguments). Graphs are captured on a private stream and launched on the
+ * solver's stream; they use runtime-managed kernel-argument memory, no
+ * caller buffer. */
+int lbm_solver_set_graph_steps(lbm_solver_t *s, int max_steps);
 
 /* Run until |mdot_k - mdot_{k-1}| / |mdot_k| < tol, where mdot is evaluated
  * every check_every steps; blocking (synchronises the stream at each check).

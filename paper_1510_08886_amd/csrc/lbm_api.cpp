@@ -169,7 +169,35 @@ struct Solver {
     alignas(16) unsigned char sc[sizeof(StepScalars<double>)];
     int64_t nodes = 0;
     int64_t steps = 0;
+    // Graph replay of step sequences (see run_graph): cached executable graphs
+    // keyed by the starting configuration and the step count, the private
+    // stream they are captured on, and the longest sequence per graph (0: off).
+    struct Graph {
+        void *pop;
+        int cur, layout, len;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t capture = nullptr;
+    int graph_steps = 0;
+    ~Solver() {
+        if (!graphs.empty() || capture) (void)hipStreamSynchronize(stream);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        if (capture) (void)hipStreamDestroy(capture);
+    }
 };
+
+// Step sequences of small problems are launch-bound (a few microseconds of
+// host overhead per launch against well under a microsecond of kernel time):
+// up to kGraphMaxSteps consecutive steps are captured once into a HIP graph
+// and replayed with one launch. Only kernel launches are captured. The step
+// kernels of every storage but FP16 deviations ignore the step counter (only
+// stochastic rounding keys on it), so a replay is bit for bit the launches it
+// recorded; FP16 runs step one launch at a time. Graphs are used for
+// population copies up to kGraphMaxBytes, where launch latency dominates.
+constexpr int kGraphMaxSteps = 256;
+constexpr size_t kGraphMaxBytes = size_t(16) << 20;
+constexpr size_t kGraphCache = 8;
 
 template <typename R>
 static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t &par, void *tab,
@@ -380,6 +408,7 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
     s->out = (double *)(base + L.off_out);
     s->stream = (hipStream_t)stream;
     s->nodes = nodes_of(*prob);
+    s->graph_steps = (st != Storage::F16DEV && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
     if (st == Storage::F64)
         fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
     else
@@ -414,20 +443,101 @@ extern "C" int lbm_init_equilibrium(lbm_solver_t *h, const double *rho_dev, cons
                      0xFFFFFFFFu);
 }
 
+// One step launch on stream st from the solver's current configuration, which
+// it then advances.
+static int step_once(Solver &s, hipStream_t st) {
+    StepBuffers b{s.pop, s.pop_other, s.layout, s.apart[s.cur], s.apart[1 - s.cur], s.invd};
+    int rc = s.L->step(b, s.tab, s.sc, st, (uint32_t)s.steps);
+    if (rc) return rc;
+    s.cur ^= 1;
+    if (s.in_place)
+        s.layout = s.layout == kLocal ? kStreamed : kLocal;
+    else
+        std::swap(s.pop, s.pop_other);
+    ++s.steps;
+    return LBM_OK;
+}
+
+// The executable graph of `len` (even) steps from the current configuration:
+// from the cache, or captured on the private stream (nothing runs during the
+// capture) and instantiated. An even count returns every alternating buffer
+// to where it started, so one graph serves every replay from this state.
+static int graph_for(Solver &s, int len, hipGraphExec_t *exec) {
+    for (auto &g : s.graphs)
+        if (g.pop == s.pop && g.cur == s.cur && g.layout == s.layout && g.len == len) {
+            *exec = g.exec;
+            return LBM_OK;
+        }
+    hipError_t e = hipSuccess;
+    if (!s.capture) e = hipStreamCreateWithFlags(&s.capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(s.capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    void *pop = s.pop, *other = s.pop_other;
+    const int cur = s.cur, layout = s.layout;
+    const int64_t steps = s.steps;
+    int rc = LBM_OK;
+    for (int k = 0; k < len && rc == LBM_OK; ++k) rc = step_once(s, s.capture);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s.capture, &graph);
+    // back to the starting configuration: the captured launches have not run
+    s.pop = pop;
+    s.pop_other = other;
+    s.cur = cur;
+    s.layout = layout;
+    s.steps = steps;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (s.graphs.size() >= kGraphCache) {
+        e = hipStreamSynchronize(s.stream);   // the oldest may still be in flight
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            return fail(LBM_E_DEVICE, std::string("stream sync: ") + hipGetErrorString(e));
+        }
+        (void)hipGraphExecDestroy(s.graphs.front().exec);
+        s.graphs.erase(s.graphs.begin());
+    }
+    s.graphs.push_back({s.pop, s.cur, s.layout, len, ex});
+    *exec = ex;
+    return LBM_OK;
+}
+
 extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
     if (!h || nsteps < 0) return fail(LBM_E_INVALID, "lbm_run: bad arguments");
     Solver &s = *reinterpret_cast<Solver *>(h);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        StepBuffers b{s.pop, s.pop_other, s.layout, s.apart[s.cur], s.apart[1 - s.cur], s.invd};
-        int rc = s.L->step(b, s.tab, s.sc, s.stream, (uint32_t)s.steps);
+    int64_t k = 0;
+    while (k < nsteps) {
+        const int64_t left = nsteps - k;
+        if (s.graph_steps >= 2 && left >= 2) {
+            const int len = (int)std::min<int64_t>(left & ~int64_t(1), s.graph_steps & ~1);
+            hipGraphExec_t ex = nullptr;
+            int rc = graph_for(s, len, &ex);
+            if (rc) return rc;
+            hipError_t e = hipGraphLaunch(ex, s.stream);
+            if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+            s.steps += len;   // an even count: buffers and layout are where they started
+            k += len;
+            continue;
+        }
+        int rc = step_once(s, s.stream);
         if (rc) return rc;
-        s.cur ^= 1;
-        if (s.in_place)
-            s.layout = s.layout == kLocal ? kStreamed : kLocal;
-        else
-            std::swap(s.pop, s.pop_other);
-        ++s.steps;
+        ++k;
     }
+    return LBM_OK;
+}
+
+extern "C" int lbm_solver_set_graph_steps(lbm_solver_t *h, int max_steps) {
+    if (!h || max_steps < 0) return fail(LBM_E_INVALID, "lbm_solver_set_graph_steps: bad arguments");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    if (max_steps > 0 && s.st == Storage::F16DEV)
+        return fail(LBM_E_UNSUPPORTED, "graph replay: FP16 stochastic rounding keys on the step");
+    s.graph_steps = std::min(max_steps, 4096);
     return LBM_OK;
 }
 

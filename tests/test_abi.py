@@ -136,3 +136,8 @@ def test_stream_copy_rejects_bad_arguments_without_a_launch():
     # 16-byte alignment and size (checked before any device call)
     assert so.lbm_stream_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), 24, None) == -1
     assert so.lbm_stream_copy(ctypes.c_void_p(8), ctypes.c_void_p(32), 32, None) == -1
+
+
+def test_set_graph_steps_rejects_bad_arguments():
+    so = lbm.lib()
+    assert so.lbm_solver_set_graph_steps(None, 4) == -1
