@@ -197,6 +197,15 @@ int lbm_init_equilibrium(lbm_solver_t *s, const double *rho_dev, const double *u
  * bit for bit those of one launch per step. */
 int lbm_run(lbm_solver_t *s, int64_t nsteps);
 
+/* Most steps lbm_run runs in one launch of one workgroup that loops over the
+ * steps (a workgroup barrier between them), for 2D problems of at most 256
+ * nodes stepped in place (0: off; at most 2^20). It removes the device-side
+ * latency between dependent launches, which dominates such problems; the
+ * arithmetic and results are those of one launch per step, FP16 stochastic
+ * rounding included. Default 4096 where allowed, else 0; LBM_E_UNSUPPORTED
+ * for a non-zero value elsewhere. Takes precedence over graph replay. */
+int lbm_solver_set_resident_steps(lbm_solver_t *s, int max_steps);
+
 /* Longest step sequence lbm_run replays from one captured HIP graph
  * (0: one launch per step; at most 4096). The default is 256 for population
  * copies up to 16 MiB, where launch latency dominates the step, and 0 above.

@@ -180,6 +180,8 @@ struct Solver {
     std::vector<Graph> graphs;
     hipStream_t capture = nullptr;
     int graph_steps = 0;
+    // Most steps per one-workgroup resident launch (0: off; see lbm_run).
+    int resident_steps = 0;
     ~Solver() {
         if (!graphs.empty() || capture) (void)hipStreamSynchronize(stream);
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -195,9 +197,18 @@ struct Solver {
 // stochastic rounding keys on it), so a replay is bit for bit the launches it
 // recorded; FP16 runs step one launch at a time. Graphs are used for
 // population copies up to kGraphMaxBytes, where launch latency dominates.
+// Problems of at most kResidentMaxNodes nodes stepped in place (2D) run up to
+// kResidentMaxSteps steps per launch in one workgroup (k_run2d), which also
+// removes the device-side latency between dependent launches; FP16 included,
+// since that kernel numbers the steps itself.
+constexpr int kResidentMaxSteps = 4096;
 constexpr int kGraphMaxSteps = 256;
 constexpr size_t kGraphMaxBytes = size_t(16) << 20;
 constexpr size_t kGraphCache = 8;
+
+static bool resident_ok(const Solver &s) {
+    return s.L->run_resident && s.in_place && s.prob.dim == 2 && s.nodes <= kResidentMaxNodes;
+}
 
 template <typename R>
 static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t &par, void *tab,
@@ -409,6 +420,7 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
     s->stream = (hipStream_t)stream;
     s->nodes = nodes_of(*prob);
     s->graph_steps = (st != Storage::F16DEV && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
+    s->resident_steps = resident_ok(*s) ? kResidentMaxSteps : 0;
     if (st == Storage::F64)
         fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
     else
@@ -514,6 +526,19 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
     int64_t k = 0;
     while (k < nsteps) {
         const int64_t left = nsteps - k;
+        if (s.resident_steps >= 2 && left >= 2) {
+            const int len = (int)std::min<int64_t>(left, s.resident_steps);
+            StepBuffers b{s.pop, s.pop_other, s.layout, s.apart[s.cur], s.apart[1 - s.cur], s.invd};
+            int rc = s.L->run_resident(b, s.tab, s.sc, s.stream, (uint32_t)s.steps, len);
+            if (rc) return rc;
+            if (len & 1) {
+                s.cur ^= 1;
+                s.layout = s.layout == kLocal ? kStreamed : kLocal;
+            }
+            s.steps += len;
+            k += len;
+            continue;
+        }
         if (s.graph_steps >= 2 && left >= 2) {
             const int len = (int)std::min<int64_t>(left & ~int64_t(1), s.graph_steps & ~1);
             hipGraphExec_t ex = nullptr;
@@ -529,6 +554,15 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
         if (rc) return rc;
         ++k;
     }
+    return LBM_OK;
+}
+
+extern "C" int lbm_solver_set_resident_steps(lbm_solver_t *h, int max_steps) {
+    if (!h || max_steps < 0) return fail(LBM_E_INVALID, "lbm_solver_set_resident_steps: bad arguments");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    if (max_steps > 0 && !resident_ok(s))
+        return fail(LBM_E_UNSUPPORTED, "resident stepping: 2D in-place problems of at most 256 nodes");
+    s.resident_steps = std::min(max_steps, 1 << 20);
     return LBM_OK;
 }
 

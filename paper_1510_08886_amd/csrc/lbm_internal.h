@@ -104,7 +104,18 @@ struct Launch {
                    hipStream_t);
     int (*importp)(void *pop, int layout, double *a_out, const double *in, const void *tab,
                    const void *sc, hipStream_t, uint32_t step);
+    // nsteps in-place steps of a problem of at most kResidentMaxNodes nodes in
+    // one workgroup launch (null where not compiled)
+    int (*run_resident)(const StepBuffers &, const void *tab, const void *sc, hipStream_t,
+                        uint32_t step0, int nsteps);
 };
+
+// Largest problem (nodes) stepped by one workgroup over many steps per launch:
+// one node per thread of a 256-thread workgroup. Measured on MI355X for nx = 1
+// channels: 3.0 against 4.0 us per step (graph replay) for D2V17 FP64 and 4.4
+// against 5.8 us for D2V37 FP32 up to 256 nodes; at 512 nodes, two nodes per
+// thread, it falls behind (5.3 against 4.5 us, 7.0 against 5.9 us).
+constexpr int64_t kResidentMaxNodes = 256;
 
 // Velocity sets with compiled kernels (library velocity order).
 struct VelSetInfo {

@@ -137,11 +137,15 @@ enum StepKind : int { kPingPong = 0, kGatherScatter = 1, kNodeLocal = 2 };
 // tile's gather into LDS with global_load_lds (LDS-limited to 8 waves per CU),
 // 64-, 128- and 512-node tiles, register caps for 6 to 8 waves per SIMD.
 template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND, bool N5>
+__device__ __forceinline__ void step_node2d(const StepBuffers &b,
+                                            const PairTable<typename St<S>::R> &t,
+                                            const StepScalars<typename St<S>::R> &s,
+                                            uint32_t step, int i, int j, uint32_t n);
+
+template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND, bool N5>
 __global__ __launch_bounds__(256)
 void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
               uint32_t step) {
-    using R = typename St<S>::R;
-    using T = typename St<S>::T;
     // ALIGNED: a 2D grid of (x tile, row) blocks, so the row, and every row
     // offset, is uniform (scalar registers); otherwise 256 consecutive nodes
     int i, j;
@@ -163,6 +167,18 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
         j = (int)(n / (uint32_t)s.nx);
         i = (int)(n - (uint32_t)j * s.nx);
     }
+    step_node2d<SET, S, ALIGNED, STREAM, KIND, N5>(b, t, s, step, i, j, n);
+}
+
+// One step of node n = (j, i): pull (or read own slots), wall fill, moments,
+// relaxation, store, wall partials.
+template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND, bool N5>
+__device__ __forceinline__ void step_node2d(const StepBuffers &b,
+                                            const PairTable<typename St<S>::R> &t,
+                                            const StepScalars<typename St<S>::R> &s,
+                                            uint32_t step, int i, int j, uint32_t n) {
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
     // BUF (aligned rows, 16-bit storage): raw buffer accesses with the row and
     // slot offsets in the scalar operand (arrays below 2 GiB), which removes
     // the vector address arithmetic. Measured on MI355X: 4% faster for the
@@ -215,6 +231,41 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
         write_own<SET, false, STREAM>(pop_at(b.pop_out), own, v);
     }
     wall_partials2d<SET, S>(v, t, s, i, j, b.a_next);
+}
+
+// Many in-place steps of a small problem (at most kResidentMaxNodes nodes) in
+// one workgroup: each step runs the per-node code of k_step2d over all nodes
+// (threads loop over nodes), the two in-place kinds alternate, and a workgroup
+// barrier, which orders the global stores and loads of the workgroup's waves
+// on their common CU, separates consecutive steps. One launch thus replaces
+// nsteps dependent launches and their device-side latency; the arithmetic and
+// the results are those of one launch per step.
+template <class SET, Storage S, bool N5>
+__global__ __launch_bounds__(256) void k_run2d(StepBuffers b, PairTable<typename St<S>::R> t,
+                                               StepScalars<typename St<S>::R> s, uint32_t step0,
+                                               int nsteps) {
+    const double *a_cur = b.a_cur;
+    double *a_next = b.a_next;
+    int layout = b.layout;
+    for (int k = 0; k < nsteps; ++k) {
+        StepBuffers bk = b;
+        bk.layout = layout;
+        bk.a_cur = a_cur;
+        bk.a_next = a_next;
+        for (uint32_t n = threadIdx.x; n < (uint32_t)s.nodes; n += blockDim.x) {
+            const int j = (int)(n / (uint32_t)s.nx);
+            const int i = (int)(n - (uint32_t)j * s.nx);
+            if (layout == kLocal)
+                step_node2d<SET, S, false, false, kGatherScatter, N5>(bk, t, s, step0 + k, i, j, n);
+            else
+                step_node2d<SET, S, false, false, kNodeLocal, N5>(bk, t, s, step0 + k, i, j, n);
+        }
+        __syncthreads();
+        double *const written = a_next;
+        a_next = const_cast<double *>(a_cur);
+        a_cur = written;
+        layout = layout == kLocal ? kStreamed : kLocal;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -425,7 +476,25 @@ struct L2 {
                            dst, layout, a_out, in, t, s, stp);
         return hip_ok(hipGetLastError(), "import kernel launch");
     }
-    static constexpr Launch table{&step, &init, &observe, &exportp, &importp};
+    static int run_resident(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
+                            uint32_t step0, int nsteps) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        if (s.nodes > kResidentMaxNodes || (b.layout != kLocal && b.layout != kStreamed))
+            return fail(LBM_E_INVALID, "resident stepping: in-place problems of at most 256 nodes");
+        bool n5 = false;
+        if constexpr (SET::Q >= 9) n5 = s.cn[5] != R(0);
+        if (n5) {
+            if constexpr (SET::Q >= 9)
+                hipLaunchKernelGGL((k_run2d<SET, S, true>), dim3(1), dim3(256), 0, st, b, t, s,
+                                   step0, nsteps);
+        } else {
+            hipLaunchKernelGGL((k_run2d<SET, S, false>), dim3(1), dim3(256), 0, st, b, t, s, step0,
+                               nsteps);
+        }
+        return hip_ok(hipGetLastError(), "resident step kernel launch");
+    }
+    static constexpr Launch table{&step, &init, &observe, &exportp, &importp, &run_resident};
 };
 
 #define LBM_2D(SET)                                                           \

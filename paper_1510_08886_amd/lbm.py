@@ -108,6 +108,7 @@ SIGNATURES = {
     "lbm_import_populations": ([_P, _P], _I),
     "lbm_solver_steps": ([_P, ctypes.POINTER(_I64)], _I),
     "lbm_solver_set_graph_steps": ([_P, _I], _I),
+    "lbm_solver_set_resident_steps": ([_P, _I], _I),
     "lbm_batch_create": ([_I, _I, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)], _I),
     "lbm_batch_destroy": ([_P], _I),
     "lbm_batch_submit": ([_P, _P, ctypes.POINTER(ProblemC), _D, _I, _I64, ctypes.c_uint64], _I),
@@ -341,6 +342,13 @@ class Solver:
 
     def run(self, nsteps: int):
         check(lib().lbm_run(self._h, int(nsteps)), "lbm_run")
+        return self
+
+    def set_resident_steps(self, max_steps: int):
+        """Most steps per one-workgroup resident launch (small 2D problems;
+        0: off)."""
+        check(lib().lbm_solver_set_resident_steps(self._h, int(max_steps)),
+              "lbm_solver_set_resident_steps")
         return self
 
     def set_graph_steps(self, max_steps: int):

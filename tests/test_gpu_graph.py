@@ -1,7 +1,11 @@
-"""Graph replay of step sequences (lbm_run on small problems): a solver that
-replays captured HIP graphs against one that launches every step, bit for bit,
-over chunks of odd and even lengths with eager work and synchronisations between
-them, so cached graphs are replayed many times from each starting state."""
+"""Multi-step launches of lbm_run on small problems, against a solver that
+launches every step, bit for bit, over chunks of odd and even lengths with eager
+work and synchronisations between them:
+
+* graph replay (captured HIP graphs, cached and replayed many times from each
+  starting state);
+* resident stepping (one workgroup loops over the steps of a 2D in-place
+  problem of at most 256 nodes, FP16 stochastic rounding included)."""
 import numpy as np
 import pytest
 
@@ -14,7 +18,7 @@ pytestmark = pytest.mark.gpu
 CHUNKS = [1, 7, 2, 33, 100, 3, 64, 64, 17]
 
 
-def _pair(name, N, nx, ny, nz=1, storage="f32", graph=16, ma=1e-2, seed=1):
+def _pair(name, N, nx, ny, nz=1, storage="f32", graph=16, ma=1e-2, seed=1, resident=0):
     from paper_1510_08886_amd import lbm
     d = lbm.Dvm.named(name)
     dim = lbm.NAMED_DVMS[name]["dim"]
@@ -23,8 +27,10 @@ def _pair(name, N, nx, ny, nz=1, storage="f32", graph=16, ma=1e-2, seed=1):
     nodes = nx * ny * nz
     rho, u = wl.random_state(nodes, dim, seed=seed, amp=1e-2)
     out = []
-    for g in (graph, 0):
+    for g, r in ((graph, resident), (0, 0)):
         s = lbm.Solver(d, prob)
+        if dim == 2 and nodes <= 256:
+            s.set_resident_steps(r)
         s.set_graph_steps(g)
         s.init(torch.from_numpy(rho), torch.from_numpy(u))
         out.append(s)
@@ -85,3 +91,43 @@ def test_graph_replay_ping_pong_path():
         assert torch.equal(a.export(), b.export()), n
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("name,N,nx,ny,storage", [
+    ("D2V17", 3, 1, 40, "f64"),      # the launch-bound FP64 channel
+    ("D2V37", 4, 20, 12, "f32"),     # 240 nodes, wall rows on both sides
+    ("D2V37", 4, 16, 16, "f16dev"),  # 256 nodes; stochastic rounding numbered per step
+    ("D2V37", 5, 1, 21, "f32"),      # Hermite order 5 variant
+    ("D2V32", 4, 5, 29, "f64"),      # halo 12, periodic wraps
+])
+def test_resident_stepping_matches_one_launch_per_step(name, N, nx, ny, storage):
+    a, b = _pair(name, N, nx, ny, 1, storage, graph=0, resident=50)
+    for k, n in enumerate(CHUNKS):
+        a.run(n)
+        b.run(n)
+        assert a.steps == b.steps
+        assert torch.equal(a.export(), b.export()), (k, n)
+        if k % 3 == 1:
+            assert a.observe()["mdot"] == b.observe()["mdot"]
+    ck = a.export().clone()
+    a.import_(ck)
+    b.import_(ck)
+    a.run(33)
+    b.run(33)
+    assert torch.equal(a.export(), b.export())
+    a.close()
+    b.close()
+
+
+def test_resident_stepping_default_and_limits():
+    from paper_1510_08886_amd import lbm
+    d = lbm.Dvm.named("D2V17")
+    big = lbm.Solver(d, lbm.Problem(dim=2, nx=17, ny=16, kn=0.1, hermite_order=3)).init()
+    with pytest.raises(lbm.LbmError):
+        big.set_resident_steps(8)      # 272 nodes: more than one node per thread
+    big.close()
+    d3 = lbm.Dvm.named("D3V39")
+    duct = lbm.Solver(d3, lbm.Problem(dim=3, nx=2, ny=8, nz=8, kn=0.1, hermite_order=3)).init()
+    with pytest.raises(lbm.LbmError):
+        duct.set_resident_steps(8)
+    duct.close()
