@@ -204,3 +204,20 @@ def test_full_size_scattering_channel_one_step():
         pg, po = populations_both(d, g, o)
         assert np.max(np.abs(pg - po) / w) <= 1e-6
     assert abs(g.observe()["mdot"] - o.observe()["mdot"]) <= 1e-5 * abs(o.observe()["mdot"])
+
+
+def test_full_size_channel_fp16_two_steps():
+    """The 2048 x 512 D2V37 channel in FP16-deviation storage (buffer-addressed
+    row-grid kernels, hardware stochastic rounding, both in-place kinds): two
+    steps against the oracle over the whole grid, to the FP16 bar."""
+    c = wl.THROUGHPUT_D2V37
+    rho = wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"])
+    d, g, o = make_pair(c["dvm"], c["N"], c["nx"], c["ny"], kn=c["kn"], ma=c["ma"],
+                        storage="f16dev", rho=rho)
+    w = d.weights[:, None, None]
+    for _ in range(2):
+        g.run(1)
+        o.run(1, nthreads=min(16, os.cpu_count() or 1))
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po) / w) <= 1e-5
+    assert abs(g.observe()["mdot"] - o.observe()["mdot"]) <= 1e-3 * abs(o.observe()["mdot"])
