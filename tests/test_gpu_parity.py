@@ -84,7 +84,8 @@ def test_low_precision_storage(storage, tol_mdot, tol_pop):
 
 
 @pytest.mark.parametrize("nx,ny", [(128, 20), (512, 13), (192, 11)])
-@pytest.mark.parametrize("storage,tol_mdot,tol_pop", [("f32", 1e-5, 1e-8), ("f16dev", 1e-3, 1e-4)])
+@pytest.mark.parametrize("storage,tol_mdot,tol_pop", [("f64", 1e-12, 1e-14), ("f32", 1e-5, 1e-8),
+                                                      ("f16dev", 1e-3, 1e-4)])
 def test_aligned_rows_in_place(storage, tol_mdot, tol_pop, nx, ny):
     """Rows of whole 64-node blocks take the row-grid kernels (tiles of 128,
     256 and 64 nodes; 1, 2 and 3 tiles per row; the per-XCD tile bands end
