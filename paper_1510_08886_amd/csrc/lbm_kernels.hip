@@ -125,23 +125,23 @@ __device__ __forceinline__ void write_gs(const P &pop, const NB &nb, Ix own, int
 // node-local -> kLocal).
 enum StepKind : int { kPingPong = 0, kGatherScatter = 1, kNodeLocal = 2 };
 
-// One thread per node, blocks of up to 256 threads: one block per (x tile,
-// row) when rows are whole 64-node blocks, else per 256 consecutive nodes.
-// Each thread issues all its loads before it decodes any, so a wavefront has its whole
-// gather in flight at once; wall slots are patched after the loads. The host
-// runs arrays of up to 512 MiB in place (on MI355X ~7% faster than ping-pong
-// for the 155 MB D2V37 channel: the array stays largely in the 256 MB
-// last-level cache) and larger ones ping-pong (~10% faster for the 1.3 GB
-// D3V39 duct). Also measured and rejected: a persistent grid with a two-stage
-// register load pipeline (occupancy 2), a persistent grid streaming the next
-// tile's gather into LDS with global_load_lds (LDS-limited to 8 waves per CU),
-// 64-, 128- and 512-node tiles, register caps for 6 to 8 waves per SIMD.
 template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND, bool N5>
 __device__ __forceinline__ void step_node2d(const StepBuffers &b,
                                             const PairTable<typename St<S>::R> &t,
                                             const StepScalars<typename St<S>::R> &s,
                                             uint32_t step, int i, int j, uint32_t n);
 
+// One thread per node, blocks of up to 256 threads: one block per (x tile,
+// row) when rows are whole 64-node blocks, else per 256 consecutive nodes.
+// Each thread issues all its loads before it decodes any, so a wavefront has
+// its whole gather in flight at once; wall slots are patched after the loads.
+// The host runs arrays of up to 512 MiB in place (on MI355X ~7% faster than
+// ping-pong for the 155 MB D2V37 channel: the array stays largely in the
+// 256 MB last-level cache) and larger ones ping-pong (10-14% faster at
+// 1.2-1.3 GB). Also measured and rejected: a persistent grid with a two-stage
+// register load pipeline (occupancy 2), a persistent grid streaming the next
+// tile's gather into LDS with global_load_lds (LDS-limited to 8 waves per CU),
+// 64-, 128- and 512-node tiles, register caps for 6 to 8 waves per SIMD.
 template <class SET, Storage S, bool ALIGNED, bool STREAM, int KIND, bool N5>
 __global__ __launch_bounds__(256)
 void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
