@@ -127,6 +127,9 @@ int validate(const Dvm &d, const lbm_problem_t &p) {
     if (p.accommodation != 1.0)
         return fail(LBM_E_UNSUPPORTED, "only the fully diffuse Maxwell wall (accommodation 1) is implemented");
     if (d.V / 2 > kMaxPairs) return fail(LBM_E_UNSUPPORTED, "velocity set too large for the kernel tables");
+    // kernels index populations and nodes with 32-bit integers
+    if ((double)d.V * (double)plane_of(nodes_of(p)) >= 4294967296.0)
+        return fail(LBM_E_UNSUPPORTED, "problem too large: V x nodes must stay below 2^32");
     return LBM_OK;
 }
 
@@ -289,10 +292,11 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->halo = d.halo;
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
-    // aligned rows: whole 64-node blocks per row; in 16-bit storage the
-    // aligned kernels address a population copy with 32-bit buffer offsets,
-    // so it must stay below 2 GiB
-    s->aligned_rows = (p.nx % 64) == 0 &&
+    // aligned rows: whole 64-node blocks per row, at most 65536 rows (the
+    // second dimension of their launch grid); in 16-bit storage the aligned
+    // kernels address a population copy with 32-bit buffer offsets, so it
+    // must stay below 2 GiB
+    s->aligned_rows = (p.nx % 64) == 0 && (int64_t)s->ny * s->nz <= 65536 &&
                       (storage_bytes(p.storage) != 2 ||
                        (double)d.V * (double)s->nodes * 2.0 < (double)(1u << 31));
     s->stream_stores = 2.0 * (double)d.V * (double)s->plane * (double)storage_bytes(p.storage) >

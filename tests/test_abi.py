@@ -141,3 +141,16 @@ def test_stream_copy_rejects_bad_arguments_without_a_launch():
 def test_set_graph_steps_rejects_bad_arguments():
     so = lbm.lib()
     assert so.lbm_solver_set_graph_steps(None, 4) == -1
+
+
+def test_problems_beyond_32_bit_indices_are_refused():
+    """Kernels index populations with 32-bit integers: V x nodes must stay below
+    2^32 (a 128 x 1024 x 1024 D3V39 duct would not)."""
+    d = lbm.Dvm.named("D3V39")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.state_bytes(d, lbm.Problem(dim=3, nx=128, ny=1024, nz=1024, kn=0.1, hermite_order=3,
+                                       storage="f32"))
+    assert e.value.code == -2
+    pop, _ = lbm.state_bytes(d, lbm.Problem(dim=3, nx=128, ny=512, nz=1024, kn=0.1,
+                                            hermite_order=3, storage="f16dev"))
+    assert pop == 2 * 39 * 128 * 512 * 1024 * 2
