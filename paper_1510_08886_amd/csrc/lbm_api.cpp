@@ -293,12 +293,13 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->nodes = nodes_of(p);
     s->plane = plane_of(s->nodes);
     // aligned rows: whole 64-node blocks per row, at most 65536 rows (the
-    // second dimension of their launch grid); in 16-bit storage the aligned
-    // kernels address a population copy with 32-bit buffer offsets, so it
-    // must stay below 2 GiB
+    // second dimension of their launch grid). Where the aligned kernels use
+    // 32-bit buffer offsets (16-bit storage; channel stencils reaching
+    // kBufferMinHalo columns) a population copy must stay below 2 GiB.
+    const bool buffer = storage_bytes(p.storage) == 2 || (p.dim == 2 && d.halo >= kBufferMinHalo);
     s->aligned_rows = (p.nx % 64) == 0 && (int64_t)s->ny * s->nz <= 65536 &&
-                      (storage_bytes(p.storage) != 2 ||
-                       (double)d.V * (double)s->nodes * 2.0 < (double)(1u << 31));
+                      (!buffer || (double)d.V * (double)s->nodes * (double)storage_bytes(p.storage) <
+                                      (double)(1u << 31));
     s->stream_stores = 2.0 * (double)d.V * (double)s->plane * (double)storage_bytes(p.storage) >
                        (double)(1u << 30);
 }

@@ -110,6 +110,10 @@ struct Launch {
                         uint32_t step0, int nsteps);
 };
 
+// Channel stencils reaching at least this far (max |e_i|, the set's halo) use
+// raw buffer addressing in the aligned step kernels whatever the storage.
+constexpr int kBufferMinHalo = 7;
+
 // Largest problem (nodes) stepped by one workgroup over many steps per launch:
 // one node per thread of a 256-thread workgroup. Measured on MI355X for nx = 1
 // channels: 3.0 against 4.0 us per step (graph replay) for D2V17 FP64 and 4.4

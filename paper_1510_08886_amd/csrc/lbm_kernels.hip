@@ -184,13 +184,15 @@ __device__ __forceinline__ void step_node2d(const StepBuffers &b,
                                             uint32_t step, int i, int j, uint32_t n) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
-    // BUF (aligned rows, 16-bit storage): raw buffer accesses with the row and
-    // slot offsets in the scalar operand (arrays below 2 GiB), which removes
-    // the vector address arithmetic. Measured on MI355X: 4% faster for the
-    // FP16 duct step, whose arithmetic outweighs its halved traffic; 0.4-2%
-    // slower for FP32 steps (the compiler then batches the stores after the
-    // collision instead of interleaving them), which keep flat addresses.
-    constexpr bool BUF = ALIGNED && sizeof(T) == 2;
+    // BUF (aligned rows; 16-bit storage, or stencils reaching 7 or more
+    // columns): raw buffer accesses with the row and slot offsets in the
+    // scalar operand (arrays below 2 GiB), which removes the vector address
+    // arithmetic. Measured on MI355X: 4% faster for the FP16 duct step, whose
+    // arithmetic outweighs its halved traffic, and 3% for the FP32 D2V32
+    // channel (25 column offsets); 0.4-2% slower for the FP32 D2V37 step (the
+    // compiler then batches the stores after the collision instead of
+    // interleaving them), which keeps flat addresses.
+    constexpr bool BUF = ALIGNED && (sizeof(T) == 2 || SET::H >= kBufferMinHalo);
     T *A = (T *)b.pop;
     auto pop_at = [&](void *base) {
         if constexpr (BUF)
