@@ -104,6 +104,23 @@ def test_aligned_rows_in_place(storage, tol_mdot, tol_pop, nx, ny):
     assert abs(og["mdot"] - oo["mdot"]) <= tol_mdot * abs(oo["mdot"])
 
 
+@pytest.mark.parametrize("nx,ny", [(128, 30), (192, 13)])
+@pytest.mark.parametrize("storage,tol_pop", [("f64", 1e-14), ("f32", 1e-8), ("f16dev", 1e-4)])
+def test_aligned_rows_wide_stencil(storage, tol_pop, nx, ny):
+    """The scattering stencil D2V32 (halo 12) on whole 64-node rows takes the
+    buffer-addressed row-grid kernels in every storage: rows 12..17 of the
+    30-row channel are off both walls, every row of the 13-row one is a wall
+    row. Both in-place kinds, element by element against the oracle."""
+    rho, u = wl.random_state(nx * ny, 2, seed=5 + nx + ny, amp=1e-3)
+    d, g, o = make_pair("D2V32", 4, nx, ny, kn=0.05, storage=storage, rho=rho, u=u)
+    w = d.weights[:, None, None]
+    for steps in (1, 6, 9):
+        g.run(steps)
+        o.run(steps)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po) / w) <= tol_pop, steps
+
+
 def test_full_size_throughput_channel_one_step_and_mass():
     """2048 x 512 FP32 D2V37 with the seeded density field: one step against the
     oracle over the whole grid, then 1000 steps conserve mass to FP32 rounding."""
