@@ -207,10 +207,16 @@ __device__ __forceinline__ void step_node2d(const StepBuffers &b,
     T raw[SET::V];
     // KIND == kNodeLocal reads only the node's own slots
     const Nbr2<SET, ALIGNED> nb(s, i, j);
+    // Wide stencils issue their reads at raised wavefront priority, so that
+    // waves still issuing loads go ahead of waves in their collision: measured
+    // 1.4% faster for the D2V32 channel, 3% slower for D2V37.
+    constexpr bool PRIO = SET::H >= kBufferMinHalo;
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
     if constexpr (KIND == kNodeLocal)
         read_local<SET>(pop, own, raw);
     else
         read_pull<SET, KIND == kGatherScatter>(pop, nb, own, raw);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     R d[SET::V];
     complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
     relax2d<SET, R, N5>(d, t, s, t.c);
