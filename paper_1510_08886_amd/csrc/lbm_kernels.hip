@@ -219,12 +219,12 @@ __device__ __forceinline__ void step_node2d(const StepBuffers &b,
     T raw[SET::V];
     // KIND == kNodeLocal reads only the node's own slots
     const Nbr2<SET, ALIGNED> nb(s, i, j);
-    // The node-local kind, and every kind of a wide stencil, issue their reads
-    // at raised wavefront priority, so that waves still issuing loads go ahead
-    // of waves in their collision. Measured on MI355X: D2V37 44.9 -> 44.4 us
-    // per step and D2V32 41.2 -> 40.7 us; the D2V37 gather/scatter kind is 4%
-    // slower with it and keeps the default priority.
-    constexpr bool PRIO = SET::H >= kBufferMinHalo || KIND == kNodeLocal;
+    // Wide stencils issue their reads at raised wavefront priority, so that
+    // waves still issuing loads go ahead of waves in their collision: measured
+    // on MI355X, D2V32 41.2 -> 40.7 us per step. For D2V37 the node-local kind
+    // gained 1% with it until its tiles ran in the alternating band order,
+    // and nothing since; its gather/scatter kind lost 4%.
+    constexpr bool PRIO = SET::H >= kBufferMinHalo;
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
     if constexpr (KIND == kNodeLocal)
         read_local<SET>(pop, own, raw);
