@@ -83,7 +83,7 @@ def test_low_precision_storage(storage, tol_mdot, tol_pop):
     assert np.max(np.abs(pg - po) / w) <= tol_pop
 
 
-@pytest.mark.parametrize("nx,ny", [(128, 20), (512, 13), (192, 11)])
+@pytest.mark.parametrize("nx,ny", [(128, 20), (512, 13), (192, 11), (64, 64)])
 @pytest.mark.parametrize("storage,tol_mdot,tol_pop", [("f64", 1e-12, 1e-14), ("f32", 1e-5, 1e-8),
                                                       ("f16dev", 1e-3, 1e-4)])
 def test_aligned_rows_in_place(storage, tol_mdot, tol_pop, nx, ny):
@@ -91,7 +91,9 @@ def test_aligned_rows_in_place(storage, tol_mdot, tol_pop, nx, ny):
     256 and 64 nodes; 1, 2 and 3 tiles per row; the per-XCD tile bands end
     mid-row when the tile count is not a multiple of 8), in 16-bit storage with
     buffer addressing: both in-place kinds (odd and even step counts) element
-    by element against the oracle."""
+    by element against the oracle. In the 64 x 64 channel each XCD band holds 8
+    tiles, so the node-local kind's wall bands take their 3 wall tiles first
+    and then run the other 5 in the opposite direction."""
     rho, u = wl.random_state(nx * ny, 2, seed=21 + nx + ny, amp=1e-3)
     d, g, o = make_pair("D2V37", 4, nx, ny, kn=0.05, storage=storage, rho=rho, u=u)
     w = d.weights[:, None, None]
@@ -104,13 +106,15 @@ def test_aligned_rows_in_place(storage, tol_mdot, tol_pop, nx, ny):
     assert abs(og["mdot"] - oo["mdot"]) <= tol_mdot * abs(oo["mdot"])
 
 
-@pytest.mark.parametrize("nx,ny", [(128, 30), (192, 13)])
+@pytest.mark.parametrize("nx,ny", [(128, 30), (192, 13), (64, 120)])
 @pytest.mark.parametrize("storage,tol_pop", [("f64", 1e-14), ("f32", 1e-8), ("f16dev", 1e-4)])
 def test_aligned_rows_wide_stencil(storage, tol_pop, nx, ny):
     """The scattering stencil D2V32 (halo 12) on whole 64-node rows takes the
     buffer-addressed row-grid kernels in every storage: rows 12..17 of the
     30-row channel are off both walls, every row of the 13-row one is a wall
-    row. Both in-place kinds, element by element against the oracle."""
+    row, and the 120-row one has XCD bands of 15 tiles whose first 12 (the
+    wall rows) come first in the node-local kind. Both in-place kinds, element
+    by element against the oracle."""
     rho, u = wl.random_state(nx * ny, 2, seed=5 + nx + ny, amp=1e-3)
     d, g, o = make_pair("D2V32", 4, nx, ny, kn=0.05, storage=storage, rho=rho, u=u)
     w = d.weights[:, None, None]
