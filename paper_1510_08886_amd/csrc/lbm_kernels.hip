@@ -160,7 +160,8 @@ void k_step2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
         // not at the end of the launch (measured 2% faster).
         // The node-local kind, which always follows a gather/scatter step,
         // walks every band the other way, so it starts on the tiles the
-        // previous step touched last (on the same XCD); the two wall bands
+        // previous step touched last, which are still in that XCD's L2 (a
+        // 16 MB copy between steps removes the gain); the two wall bands
         // first take their HN wall rows, then the rest of the band in that
         // opposite direction. Measured on MI355X: D2V37 44.4 -> 43.0 us and
         // D2V32 40.7 -> 39.9 us per step; reversing the wall bands too, wall
