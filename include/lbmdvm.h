@@ -58,6 +58,16 @@ enum lbm_storage {
                         ~6e-8 of w rho0, so slow relaxations stagnate early */
 };
 
+/* Population layout in HBM. Both give identical results; the choice only
+ * moves the memory traffic. LBM_LAYOUT_AUTO keeps one array stepped in place
+ * up to 512 MiB per copy (it stays largely in the 256 MB last-level cache) and
+ * two ping-pong copies above that. */
+enum lbm_layout {
+    LBM_LAYOUT_AUTO = 0,
+    LBM_LAYOUT_IN_PLACE = 1,  /* one array; steps alternate two in-place kinds */
+    LBM_LAYOUT_PING_PONG = 2  /* two copies; each step pulls from one into the other */
+};
+
 /* Problem statement (Section V / VI of the paper). */
 typedef struct {
     int dim;              /* 2: channel (walls at y); 3: duct (walls at y and z) */
@@ -71,6 +81,7 @@ typedef struct {
     double accommodation; /* 1 = fully diffuse Maxwell wall (only value supported) */
     double rho0;          /* reference density (deviation storage, initial state) */
     int storage;          /* enum lbm_storage */
+    int layout;           /* enum lbm_layout: how the populations are kept in HBM */
 } lbm_problem_t;
 
 /* Derived per-solve scalars. */
@@ -165,17 +176,19 @@ int lbm_profile_analysis(const double *u, int ny, lbm_profile_stats_t *stats, do
 int lbm_params(const lbm_dvm_t *dvm, const lbm_problem_t *prob, lbm_params_t *out);
 
 /* Bytes the caller must provide: the population buffer (*pop_bytes: one copy of
- * the populations up to 512 MiB per copy, two copies above) and the scratch
- * buffer (*scratch_bytes). */
+ * the populations when stepped in place, two copies for ping-pong; see
+ * enum lbm_layout) and the scratch buffer (*scratch_bytes). LBM_E_INVALID for
+ * an unknown layout. */
 int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, size_t *pop_bytes,
                     size_t *scratch_bytes);
 
 /* Create a solver over caller device buffers pop_a (populations, >= pop_bytes)
  * and scratch (>= scratch_bytes), both aligned to 256 bytes, on the HIP stream
- * `stream` (hipStream_t; NULL = default stream). Up to 512 MiB of populations
- * the update runs in place in one array (each step reads and writes the same
- * locations per node, alternating two layouts); above that pop_a holds two
- * copies, stepped ping-pong. pop_b is not used and may be NULL.
+ * `stream` (hipStream_t; NULL = default stream). In place (prob->layout, by
+ * default up to 512 MiB of populations) the update runs in one array (each
+ * step reads and writes the same locations per node, alternating two
+ * layouts); otherwise pop_a holds two copies, stepped ping-pong. pop_b is not
+ * used and may be NULL.
  * Validation (LBM_E_INVALID): ny (and nz in 3D) >= the largest |e_n|;
  * 2 <= N <= (Q+1)/2; kn > 0; g.n = 0; sizes positive. accommodation != 1 gives
  * LBM_E_UNSUPPORTED, as do N > 5 and a velocity set without a compiled kernel
@@ -205,6 +218,17 @@ int lbm_run(lbm_solver_t *s, int64_t nsteps);
  * rounding included. Default 4096 where allowed, else 0; LBM_E_UNSUPPORTED
  * for a non-zero value elsewhere. Takes precedence over graph replay. */
 int lbm_solver_set_resident_steps(lbm_solver_t *s, int max_steps);
+
+/* Two time steps per launch for 2D problems stepped ping-pong (temporal
+ * blocking): each workgroup computes step t for its tile widened by the
+ * stencil's reach and keeps it in LDS, then step t + 1 of the tile, so a node
+ * is read and written in HBM once per two lattice updates. The arithmetic and
+ * results are bit for bit those of one launch per step. on = 0 switches it
+ * off; band_rows is the height of each workgroup's band of rows (0: chosen
+ * for the device). Compiled for the 2D sets reaching at most 4 nodes; off by
+ * default; LBM_E_UNSUPPORTED for on != 0 elsewhere. lbm_run takes two-step
+ * launches while two or more steps remain. */
+int lbm_solver_set_pair_steps(lbm_solver_t *s, int on, int band_rows);
 
 /* Longest step sequence lbm_run replays from one captured HIP graph
  * (0: one launch per step; at most 4096). The default is 256 for population

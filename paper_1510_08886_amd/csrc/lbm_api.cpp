@@ -72,7 +72,8 @@ Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
     Layout L;
     const int64_t nodes = nodes_of(p);
     L.copy_bytes = align_up((size_t)d.V * plane_of(nodes) * storage_bytes(p.storage));
-    L.in_place = L.copy_bytes <= kInPlaceMaxBytes;
+    L.in_place = p.layout == LBM_LAYOUT_IN_PLACE ||
+                 (p.layout == LBM_LAYOUT_AUTO && L.copy_bytes <= kInPlaceMaxBytes);
     L.pop_bytes = L.in_place ? L.copy_bytes : 2 * L.copy_bytes;
     L.apart_bytes = align_up(sizeof(double) * 4 * std::max(1, d.halo) * face_elems(p));
     L.partial_bytes = align_up(sizeof(double) * 2 * observe_blocks(nodes));
@@ -124,6 +125,9 @@ int validate(const Dvm &d, const lbm_problem_t &p) {
     if (!p.g_set && !(std::isfinite(p.ma))) return fail(LBM_E_INVALID, "ma must be finite");
     if (!(p.rho0 > 0)) return fail(LBM_E_INVALID, "rho0 must be positive");
     if (storage_bytes(p.storage) == 0) return fail(LBM_E_INVALID, "unknown storage");
+    if (p.layout != LBM_LAYOUT_AUTO && p.layout != LBM_LAYOUT_IN_PLACE &&
+        p.layout != LBM_LAYOUT_PING_PONG)
+        return fail(LBM_E_INVALID, "unknown population layout");
     if (p.accommodation != 1.0)
         return fail(LBM_E_UNSUPPORTED, "only the fully diffuse Maxwell wall (accommodation 1) is implemented");
     if (d.V / 2 > kMaxPairs) return fail(LBM_E_UNSUPPORTED, "velocity set too large for the kernel tables");
@@ -185,6 +189,9 @@ struct Solver {
     int graph_steps = 0;
     // Most steps per one-workgroup resident launch (0: off; see lbm_run).
     int resident_steps = 0;
+    // Two ping-pong steps per launch (Launch::pair) and its band height (0: auto).
+    bool pair_steps = false;
+    int pair_band_rows = 0;
     ~Solver() {
         if (!graphs.empty() || capture) (void)hipStreamSynchronize(stream);
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -212,6 +219,8 @@ constexpr size_t kGraphCache = 8;
 static bool resident_ok(const Solver &s) {
     return s.L->run_resident && s.in_place && s.prob.dim == 2 && s.nodes <= kResidentMaxNodes;
 }
+
+static bool pair_ok(const Solver &s) { return s.L->pair && !s.in_place; }
 
 template <typename R>
 static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t &par, void *tab,
@@ -426,6 +435,9 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
     s->nodes = nodes_of(*prob);
     s->graph_steps = (st != Storage::F16DEV && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
     s->resident_steps = resident_ok(*s) ? kResidentMaxSteps : 0;
+    // two steps per launch where compiled, for ping-pong problems not already
+    // stepped from graphs
+    s->pair_steps = false;
     if (st == Storage::F64)
         fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
     else
@@ -544,6 +556,16 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
             k += len;
             continue;
         }
+        if (s.pair_steps && left >= 2) {
+            StepBuffers b{s.pop, s.pop_other, s.layout, s.apart[s.cur], s.apart[1 - s.cur], s.invd};
+            int rc = s.L->pair(b, s.tab, s.sc, s.stream, (uint32_t)s.steps, s.pair_band_rows);
+            if (rc) return rc;
+            s.cur ^= 1;
+            std::swap(s.pop, s.pop_other);
+            s.steps += 2;
+            k += 2;
+            continue;
+        }
         if (s.graph_steps >= 2 && left >= 2) {
             const int len = (int)std::min<int64_t>(left & ~int64_t(1), s.graph_steps & ~1);
             hipGraphExec_t ex = nullptr;
@@ -568,6 +590,17 @@ extern "C" int lbm_solver_set_resident_steps(lbm_solver_t *h, int max_steps) {
     if (max_steps > 0 && !resident_ok(s))
         return fail(LBM_E_UNSUPPORTED, "resident stepping: 2D in-place problems of at most 256 nodes");
     s.resident_steps = std::min(max_steps, 1 << 20);
+    return LBM_OK;
+}
+
+extern "C" int lbm_solver_set_pair_steps(lbm_solver_t *h, int on, int band_rows) {
+    if (!h || band_rows < 0) return fail(LBM_E_INVALID, "lbm_solver_set_pair_steps: bad arguments");
+    Solver &s = *reinterpret_cast<Solver *>(h);
+    if (on && !pair_ok(s))
+        return fail(LBM_E_UNSUPPORTED,
+                    "two steps per launch: 2D ping-pong problems of a set with a compiled kernel");
+    s.pair_steps = on != 0;
+    s.pair_band_rows = band_rows;
     return LBM_OK;
 }
 

@@ -597,6 +597,9 @@ extern "C" int lbm_batch_submit(lbm_batch_t *h, const lbm_dvm_t *dvm, const lbm_
         }
     if (b.lds_bytes(r) > b.max_lds || (size_t)prob->ny > 2u * 1024u)
         return fail(LBM_E_NO_MEMORY, "lbm_batch_submit: channel does not fit one workgroup's LDS");
+    // a thread steps at most two rows: refuse here rather than after admission
+    if (prob->ny > 2 * b.threads)
+        return fail(LBM_E_INVALID, "lbm_batch_submit: ny above twice the workgroup size");
     if (b.state_bytes(r) > b.pool_bytes - b.off_heap)
         return fail(LBM_E_NO_MEMORY, "lbm_batch_submit: channel larger than the pool");
     b.queue.push_back(r);
@@ -672,6 +675,12 @@ extern "C" int lbm_batch_tune(lbm_batch_t *h, int threads, int quantum) {
     if (!h || threads < 64 || threads > 1024 || threads % 64 || quantum < 1)
         return fail(LBM_E_INVALID, "lbm_batch_tune: bad arguments");
     Batch &b = *reinterpret_cast<Batch *>(h);
+    int maxny = 0;
+    for (auto &r : b.queue) maxny = std::max(maxny, r.ny);
+    for (auto &a : b.active) maxny = std::max(maxny, a.req.ny);
+    if (2 * threads < maxny)
+        return fail(LBM_E_INVALID, "lbm_batch_tune: a queued or resident channel has more than "
+                                   "twice that many rows");
     b.threads = threads;
     b.quantum = quantum;
     return LBM_OK;

@@ -108,6 +108,11 @@ struct Launch {
     // one workgroup launch (null where not compiled)
     int (*run_resident)(const StepBuffers &, const void *tab, const void *sc, hipStream_t,
                         uint32_t step0, int nsteps);
+    // two ping-pong steps in one launch (kDirect pop -> kDirect pop_out; a_cur
+    // -> a_next): the intermediate state stays on chip (null where not
+    // compiled). band_rows = rows per workgroup band (0: chosen for the chip).
+    int (*pair)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, uint32_t step,
+                int band_rows);
 };
 
 // Channel stencils reaching at least this far (max |e_i|, the set's halo) use

@@ -27,6 +27,7 @@
 // is the column of the fluid node next to the crossing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "lbm_node2d.h"
@@ -297,6 +298,141 @@ __global__ __launch_bounds__(256) void k_run2d(StepBuffers b, PairTable<typename
 }
 
 // ---------------------------------------------------------------------------
+// Two ping-pong steps per launch (temporal blocking). A workgroup owns a tile
+// of BX columns of a band of rows and sweeps it upwards in chunks of RR rows.
+// Step t is computed for the tile widened by the stencil reach (H columns and
+// HN rows on each side, the extra nodes computed by both neighbours), from
+// the source copy in HBM, and kept in a ring of RR + 2 HN rows in LDS; step
+// t + 1 of each chunk then pulls from the ring and goes to the destination
+// copy. Per two lattice updates a node is thus read once and written once in
+// HBM. Workgroups never exchange data, so nothing waits on another workgroup;
+// inside one, barriers order the ring's writes and reads. The per-node
+// arithmetic, the stochastic-rounding keys and the FP64 wall partials are
+// those of two kPingPong launches, so the results are bit for bit the same.
+//
+// The wall partials that step t writes for step t + 1 (only the tile's own
+// columns are ever needed) stay in LDS: a band touching a wall computes all of
+// that wall's rows in step t (its widened rows reach them), so every wall row
+// of step t + 1 finds its column's partials.
+// ---------------------------------------------------------------------------
+template <class SET, typename T>
+struct PairTile {
+    static constexpr int H = SET::H, HN = SET::HN, V = SET::V;
+    static constexpr size_t kLds = 156 * 1024;   // of the 160 KB of a gfx950 CU
+    static constexpr size_t bytes(int bx, int rr) {
+        return (size_t)(rr + 2 * HN) * (bx + 2 * H) * V * sizeof(T) + (size_t)2 * HN * bx * 8;
+    }
+    static constexpr int pick_bx() { return bytes(64, 8) <= kLds ? 64 : 32; }
+    static constexpr int pick_rr(int bx) {
+        return bytes(bx, 16) <= kLds && 16 * (bx + 2 * H) <= 1024 ? 16
+               : bytes(bx, 8) <= kLds                                      ? 8
+               : bytes(bx, 4) <= kLds                                      ? 4
+                                                                           : 2;
+    }
+    static constexpr int BX = pick_bx();
+    static constexpr int RR = pick_rr(BX);
+    static constexpr int EW = BX + 2 * H;          // ring row pitch (columns)
+    static constexpr int RING = RR + 2 * HN;       // ring rows
+    static constexpr bool ok = bytes(BX, RR) <= kLds && H <= 4;
+    // threads: one step-t node of a chunk each
+    static constexpr int NT = ((RR * EW + 63) / 64) * 64 > 1024 ? 1024 : ((RR * EW + 63) / 64) * 64;
+};
+
+template <class SET, Storage S, bool ALIGNED, bool STREAM, bool N5>
+__global__ __launch_bounds__((PairTile<SET, typename St<S>::T>::NT))
+void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
+              uint32_t step, int band_rows) {
+    using R = typename St<S>::R;
+    using T = typename St<S>::T;
+    using TL = PairTile<SET, T>;
+    constexpr int H = SET::H, HN = SET::HN, V = SET::V, NR = SET::NR;
+    constexpr int BX = TL::BX, RR = TL::RR, EW = TL::EW, RING = TL::RING;
+    __shared__ T ring[RING * V * EW];      // [row mod RING][alpha][column]
+    __shared__ double ap[2 * HN * BX];     // step-t partials of the tile's columns [face][row][col]
+
+    // tile of this workgroup: XCD x (workgroups go to the 8 XCDs round-robin)
+    // takes a contiguous run of tiles in (band, strip) order, so the strips
+    // that share halo columns share an L2
+    const int nx = s.nx, ny = s.ny;
+    const uint32_t total = gridDim.x, id = blockIdx.x, xcd = id & 7u;
+    const uint32_t lin = xcd * (total >> 3) + min(xcd, total & 7u) + (id >> 3);
+    const int nstrips = (nx + BX - 1) / BX;
+    const int strip = (int)(lin % (uint32_t)nstrips), band = (int)(lin / (uint32_t)nstrips);
+    const int x0 = strip * BX, ncols = min(BX, nx - x0);
+    const int y0 = band * band_rows, y1 = min(y0 + band_rows, ny);
+    const int a = max(y0 - HN, 0);         // first step-t row of the band
+    const T *A = (const T *)b.pop;
+    const GlobalPop<T> src{const_cast<T *>(A)};
+    const GlobalPop<T> dst{(T *)b.pop_out};
+
+    // step t of rows [lo, hi), columns x0 - H .. x0 + ncols + H - 1, into the ring
+    auto first = [&](int lo, int hi) {
+        const int w = ncols + 2 * H;
+        const int n1 = (hi - lo) * w;
+        for (int e = threadIdx.x; e < n1; e += blockDim.x) {
+            const int rl = e / w, c = e - rl * w;
+            const int j = lo + rl;
+            const int i = wrap_col(x0 - H + c, nx, H);
+            const uint32_t n = (uint32_t)j * (uint32_t)nx + (uint32_t)i;
+            T raw[V];
+            {
+                const Nbr2<SET, ALIGNED> nb(s, i, j);
+                read_pull<SET, false>(src, nb, Ix{aos_base<V>(n), 0u, 0u}, raw);
+            }
+            R d[V];
+            complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
+            relax2d<SET, R, N5>(d, t, s, t.c);
+            T v[V];
+            encode_all<SET, S, true>(d, t, n, step, v);
+            T *rw = ring + (size_t)((j - a) % RING) * (V * EW) + c;
+#pragma unroll
+            for (int q = 0; q < V; ++q) rw[q * EW] = v[q];
+            if (c >= H && c < H + ncols) wall_partials2d_col<SET, S>(v, t, s, j, ap + (c - H), BX);
+        }
+    };
+    // step t + 1 of rows [lo, hi), the tile's own columns, from the ring to HBM
+    auto second = [&](int lo, int hi) {
+        const int n2 = (hi - lo) * BX;
+        for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+            const int rl = e / BX, il = e - rl * BX;
+            if (il >= ncols) continue;
+            const int j = lo + rl, i = x0 + il;
+            const uint32_t n = (uint32_t)j * (uint32_t)nx + (uint32_t)i;
+            auto at = [&](int row, int slot, int col) -> T {
+                const int jr = min(max(row, 0), ny - 1);
+                return ring[(size_t)((jr - a) % RING) * (V * EW) + slot * EW + col];
+            };
+            T raw[V];
+            if constexpr (NR) raw[0] = at(j, 0, il + H);
+            for_pairs<SET::NP>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                constexpr int ex = SET::EX[p], ey = SET::EY[p];
+                raw[NR + 2 * p] = at(j - ey, NR + 2 * p, il + H - ex);
+                raw[NR + 2 * p + 1] = at(j + ey, NR + 2 * p + 1, il + H + ex);
+            });
+            R d[V];
+            complete2d_col<SET, S>(raw, ap + il, BX, t, s, j, d);
+            relax2d<SET, R, N5>(d, t, s, t.c);
+            T v[V];
+            encode_all<SET, S, true>(d, t, n, step + 1u, v);
+            write_own<SET, false, STREAM>(dst, Ix{aos_base<V>(n), 0u, 0u}, v);
+            wall_partials2d<SET, S>(v, t, s, i, j, b.a_next);
+        }
+    };
+
+    int ready = a;   // step-t rows [a, ready) are in the ring
+    for (int lo = y0; lo < y1; lo += RR) {
+        const int hi = min(lo + RR, y1);
+        const int need = min(hi + HN, ny);
+        first(ready, need);
+        ready = need;
+        __syncthreads();
+        second(lo, hi);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // observation: moments of the streamed state, FP64 partial sums per block
 // ---------------------------------------------------------------------------
 template <class SET, Storage S>
@@ -522,7 +658,53 @@ struct L2 {
         }
         return hip_ok(hipGetLastError(), "resident step kernel launch");
     }
-    static constexpr Launch table{&step, &init, &observe, &exportp, &importp, &run_resident};
+    // Two steps per launch (k_pair2d). Bands: the fewest that give every CU
+    // at least one workgroup, so that the rows recomputed at band edges stay
+    // few; a forced band height (tests, tuning) may be anything >= 1.
+    static int pair(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
+                    uint32_t stp, int band_rows) {
+        using TL = PairTile<SET, typename St<S>::T>;
+        if constexpr (!TL::ok) {
+            return fail(LBM_E_UNSUPPORTED, "two-step kernel: stencil too wide for the LDS ring");
+        } else {
+            const auto &t = *(const PairTable<R> *)tab;
+            const auto &s = *(const StepScalars<R> *)sc;
+            if (b.layout != kDirect || !b.pop_out)
+                return fail(LBM_E_INVALID, "two-step kernel: needs two population copies");
+            const int nstrips = (s.nx + TL::BX - 1) / TL::BX;
+            if (band_rows <= 0) {
+                int dev = 0, cus = 256;
+                if (hipGetDevice(&dev) == hipSuccess)
+                    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+                const int bands = std::max(1, std::min(s.ny, (cus + nstrips - 1) / nstrips));
+                band_rows = (s.ny + bands - 1) / bands;
+                band_rows = (band_rows + TL::RR - 1) / TL::RR * TL::RR;
+            }
+            const int bands = (s.ny + band_rows - 1) / band_rows;
+            const dim3 g((unsigned)(nstrips * bands)), bl(TL::NT);
+            bool n5 = false;
+            if constexpr (SET::Q >= 9) n5 = s.cn[5] != R(0);
+#define LBM_PAIR(AL, STR, N5V) \
+    hipLaunchKernelGGL((k_pair2d<SET, S, AL, STR, N5V>), g, bl, 0, st, b, t, s, stp, band_rows)
+            const bool al = s.nx % 64 == 0, str = s.stream_stores != 0;
+            if (n5) {
+                if constexpr (SET::Q >= 9) {
+                    if (al && str) LBM_PAIR(true, true, true);
+                    else if (al) LBM_PAIR(true, false, true);
+                    else LBM_PAIR(false, false, true);
+                }
+            } else {
+                if (al && str) LBM_PAIR(true, true, false);
+                else if (al) LBM_PAIR(true, false, false);
+                else LBM_PAIR(false, false, false);
+            }
+#undef LBM_PAIR
+            return hip_ok(hipGetLastError(), "two-step kernel launch");
+        }
+    }
+    static constexpr Launch table{&step,    &init,         &observe, &exportp,
+                                  &importp, &run_resident,
+                                  PairTile<SET, typename St<S>::T>::ok ? &pair : nullptr};
 };
 
 #define LBM_2D(SET)                                                           \

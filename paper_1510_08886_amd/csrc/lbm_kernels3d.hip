@@ -612,7 +612,7 @@ struct L3 {
                            dst, layout, a_out, in, t, s, stp);
         return hip_ok(hipGetLastError(), "3D import kernel launch");
     }
-    static constexpr Launch table{&step, &init, &observe, &exportp, &importp, nullptr};
+    static constexpr Launch table{&step, &init, &observe, &exportp, &importp, nullptr, nullptr};
 };
 
 #define LBM_3D(SET)                                                           \

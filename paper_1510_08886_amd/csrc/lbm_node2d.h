@@ -125,17 +125,18 @@ __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
 // ---------------------------------------------------------------------------
 // raw[] holds the stored values at the (clamped) pull sources; decode them to
 // deviations and replace the values whose source lies outside the channel by
-// the diffuse-wall populations. a_cur holds the FP64 partials of the column
-// as [face][row < HN][column] with column stride nx.
+// the diffuse-wall populations. a_col points at the FP64 partials of the
+// node's column, [face][row < HN] with row stride `stride` (the global
+// partials [face][row][column] have stride nx).
 template <class SET, Storage S>
-__device__ __forceinline__ void complete2d(const typename St<S>::T (&raw)[SET::V],
-                                           const double *__restrict__ a_cur,
-                                           const PairTable<typename St<S>::R> &t,
-                                           const StepScalars<typename St<S>::R> &s, int i, int j,
-                                           typename St<S>::R (&d)[SET::V]) {
+__device__ __forceinline__ void complete2d_col(const typename St<S>::T (&raw)[SET::V],
+                                               const double *__restrict__ a_col, int stride,
+                                               const PairTable<typename St<S>::R> &t,
+                                               const StepScalars<typename St<S>::R> &s, int j,
+                                               typename St<S>::R (&d)[SET::V]) {
     using R = typename St<S>::R;
     constexpr int NR = SET::NR, HN = SET::HN;
-    const int nx = s.nx, ny = s.ny;
+    const int ny = s.ny;
     if constexpr (NR) d[0] = decode_dev<S>(raw[0], t.wr00);
     for_pairs<SET::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
@@ -147,8 +148,8 @@ __device__ __forceinline__ void complete2d(const typename St<S>::T (&raw)[SET::V
         double alo = 0.0, ahi = 0.0;
 #pragma unroll
         for (int r = 0; r < HN; ++r) {
-            alo += a_cur[r * nx + i];
-            ahi += a_cur[(HN + r) * nx + i];
+            alo += a_col[r * stride];
+            ahi += a_col[(HN + r) * stride];
         }
         const double rlo = alo * s.invD[0], rhi = ahi * s.invD[1];
         // wall population w (rho_eff (1 - dt/2 g.xi)) as a deviation from w rho0
@@ -173,16 +174,27 @@ __device__ __forceinline__ void complete2d(const typename St<S>::T (&raw)[SET::V
     }
 }
 
+template <class SET, Storage S>
+__device__ __forceinline__ void complete2d(const typename St<S>::T (&raw)[SET::V],
+                                           const double *__restrict__ a_cur,
+                                           const PairTable<typename St<S>::R> &t,
+                                           const StepScalars<typename St<S>::R> &s, int i, int j,
+                                           typename St<S>::R (&d)[SET::V]) {
+    complete2d_col<SET, S>(raw, a_cur + i, s.nx, t, s, j, d);
+}
+
 // FP64 partial, per wall row and column, of the just-stored populations that
 // leave through each face in the next streaming step (plus the constant
-// w rho0 parts for deviation storages).
+// w rho0 parts for deviation storages), into the column's partials a_col
+// ([face][row < HN], row stride `stride`).
 template <class SET, Storage S>
-__device__ __forceinline__ void wall_partials2d(const typename St<S>::T (&v)[SET::V],
-                                                const PairTable<typename St<S>::R> &t,
-                                                const StepScalars<typename St<S>::R> &s, int i,
-                                                int j, double *__restrict__ a_next) {
+__device__ __forceinline__ void wall_partials2d_col(const typename St<S>::T (&v)[SET::V],
+                                                    const PairTable<typename St<S>::R> &t,
+                                                    const StepScalars<typename St<S>::R> &s,
+                                                    int j, double *__restrict__ a_col,
+                                                    int stride) {
     constexpr int NR = SET::NR, HN = SET::HN;
-    const int nx = s.nx, ny = s.ny;
+    const int ny = s.ny;
     if (j < HN || j >= ny - HN) {
         double lo = 0.0, hi = 0.0;
         for_pairs<SET::NP>([&](auto pc) {
@@ -197,9 +209,17 @@ __device__ __forceinline__ void wall_partials2d(const typename St<S>::T (&v)[SET
                 if (j - ey >= ny) hi += vm;
             }
         });
-        if (j < HN) a_next[j * nx + i] = s.kA[0][j] + lo;
-        if (j >= ny - HN) a_next[(HN + (ny - 1 - j)) * nx + i] = s.kA[1][ny - 1 - j] + hi;
+        if (j < HN) a_col[j * stride] = s.kA[0][j] + lo;
+        if (j >= ny - HN) a_col[(HN + (ny - 1 - j)) * stride] = s.kA[1][ny - 1 - j] + hi;
     }
+}
+
+template <class SET, Storage S>
+__device__ __forceinline__ void wall_partials2d(const typename St<S>::T (&v)[SET::V],
+                                                const PairTable<typename St<S>::R> &t,
+                                                const StepScalars<typename St<S>::R> &s, int i,
+                                                int j, double *__restrict__ a_next) {
+    wall_partials2d_col<SET, S>(v, t, s, j, a_next + i, s.nx);
 }
 
 }  // namespace lbm

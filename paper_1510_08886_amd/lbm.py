@@ -19,6 +19,7 @@ LBM_OK = 0
 ERRORS = {-1: "LBM_E_INVALID", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_NO_MEMORY",
           -4: "LBM_E_QUADRATURE", -5: "LBM_E_DEVICE", -6: "LBM_E_NOT_CONVERGED"}
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "f32raw": 3}
+LAYOUT = {"auto": 0, "in_place": 1, "ping_pong": 2}
 
 # Velocity groups of the three models used for channels and ducts: generators,
 # dimension, quadrature order, Hermite order of the equilibrium.
@@ -46,7 +47,7 @@ class ProblemC(ctypes.Structure):
                 ("nz", ctypes.c_int), ("kn", ctypes.c_double), ("ma", ctypes.c_double),
                 ("g_set", ctypes.c_int), ("g", ctypes.c_double * 3),
                 ("hermite_order", ctypes.c_int), ("accommodation", ctypes.c_double),
-                ("rho0", ctypes.c_double), ("storage", ctypes.c_int)]
+                ("rho0", ctypes.c_double), ("storage", ctypes.c_int), ("layout", ctypes.c_int)]
 
 
 class ParamsC(ctypes.Structure):
@@ -108,6 +109,7 @@ SIGNATURES = {
     "lbm_import_populations": ([_P, _P], _I),
     "lbm_solver_steps": ([_P, ctypes.POINTER(_I64)], _I),
     "lbm_solver_set_graph_steps": ([_P, _I], _I),
+    "lbm_solver_set_pair_steps": ([_P, _I, _I], _I),
     "lbm_solver_set_resident_steps": ([_P, _I], _I),
     "lbm_batch_create": ([_I, _I, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)], _I),
     "lbm_batch_destroy": ([_P], _I),
@@ -266,6 +268,7 @@ class Problem:
     accommodation: float = 1.0
     rho0: float = 1.0
     storage: str = "f64"
+    layout: str = "auto"
 
     def to_c(self) -> ProblemC:
         p = ProblemC()
@@ -279,6 +282,7 @@ class Problem:
         p.accommodation = self.accommodation
         p.rho0 = self.rho0
         p.storage = STORAGE[self.storage]
+        p.layout = LAYOUT[self.layout]
         return p
 
 
@@ -349,6 +353,13 @@ class Solver:
         0: off)."""
         check(lib().lbm_solver_set_resident_steps(self._h, int(max_steps)),
               "lbm_solver_set_resident_steps")
+        return self
+
+    def set_pair_steps(self, on: bool, band_rows: int = 0):
+        """Two time steps per launch (2D ping-pong problems; bitwise the same
+        results); band_rows 0 lets the library choose."""
+        check(lib().lbm_solver_set_pair_steps(self._h, int(bool(on)), int(band_rows)),
+              "lbm_solver_set_pair_steps")
         return self
 
     def set_graph_steps(self, max_steps: int):

@@ -56,9 +56,12 @@ def batched_sweep(channels, dvm_name="D2V37", storage="f32", tol=1e-8, check_eve
 
 def plain_sweep(channels, dvm_name="D2V37", storage="f32", tol=1e-8, check_every=100,
                 max_steps=2_000_000, budget_s=None):
-    """The same channels one at a time, one step-kernel launch per step and a
-    mass-flow check every check_every steps (lbm_run_to_tol). Optionally stop
-    after budget_s seconds; returns the results done and their total time."""
+    """The same channels one at a time through the single-solve path
+    (lbm_run_to_tol, a mass-flow check every check_every steps): channels of
+    at most 256 rows step in one-workgroup resident launches of many steps,
+    larger ones replay captured graphs of up to 256 step launches. Optionally
+    stop after budget_s seconds; returns the results done and their total
+    time."""
     import torch
 
     d = lbm.Dvm.named(dvm_name)

@@ -19,7 +19,7 @@ EXTRA_SETS = {"D3V15": (3, [(0, 0, 0), (2, 0, 0), (1, 1, 1)], 5)}
 
 # scattering stencils with compiled kernels, built on both sides from the
 # paper's printed tables (c and weights)
-TABLE_SETS = ("D2V32", "D3V96")
+TABLE_SETS = ("D2V32", "D3V96", "D2V16", "D2V33")
 
 
 def dvm_pair(name):
@@ -37,13 +37,13 @@ def dvm_pair(name):
 
 
 def make_pair(name, N, nx, ny, nz=1, kn=0.1, ma=1e-3, storage="f64", rho=None, u=None,
-              walls_z=False):
+              walls_z=False, layout="auto"):
     import torch
     from paper_1510_08886_amd import lbm
 
     d, od = dvm_pair(name)
     prob = lbm.Problem(dim=d.dim, nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, hermite_order=N,
-                       storage=storage)
+                       storage=storage, layout=layout)
     g = lbm.Solver(d, prob)
     o = stepper.OracleSolver(od, nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, N=N,
                              walls_z=walls_z or d.dim == 3)

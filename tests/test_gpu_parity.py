@@ -243,3 +243,178 @@ def test_full_size_channel_fp16_two_steps():
         pg, po = populations_both(d, g, o)
         assert np.max(np.abs(pg - po) / w) <= 1e-5
     assert abs(g.observe()["mdot"] - o.observe()["mdot"]) <= 1e-3 * abs(o.observe()["mdot"])
+
+
+@pytest.mark.parametrize("name,N,nx,ny", [
+    ("D2V16", 4, 70, 13),    # no rest velocity, halo 4: two x-tiles plus a ragged tail
+    ("D2V16", 3, 3, 9),      # nx < |e_x| = 4: repeated periodic wraps
+    ("D2V16", 4, 128, 7),    # aligned rows, ny < 2 * halo: every row a wall row
+    ("D2V33", 5, 70, 13),    # quadrature order 9 with the order-5 equilibrium
+    ("D2V33", 4, 64, 4),     # ny = largest |e_y| = 4, aligned rows
+    ("D2V33", 3, 1, 21),     # streamwise-invariant column
+])
+@pytest.mark.parametrize("layout", ["in_place", "ping_pong"])
+def test_minimal_sets_s5_s6_elementwise(name, N, nx, ny, layout):
+    """The minimal models of sets S5 (D2V16) and S6 (D2V33), built on both
+    sides from their printed tables (tab:dvmSet5Amin, tab:dvmSet6Amin): a random
+    state stepped in place and ping-pong, element by element against the
+    oracle (FP64 to 1e-14)."""
+    rho, u = wl.random_state(nx * ny, 2, seed=nx * 17 + ny, amp=2e-2)
+    d, g, o = make_pair(name, N, nx, ny, kn=0.07, ma=2e-2, rho=rho, u=u, layout=layout)
+    for steps in (1, 4):
+        g.run(steps)
+        o.run(steps)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po)) <= 1e-14, steps
+    og, oo = g.observe(), o.observe()
+    np.testing.assert_allclose(og["rho"].cpu().numpy(), oo["rho"], rtol=1e-14)
+    assert abs(og["mdot"] - oo["mdot"]) <= 1e-12 * abs(oo["mdot"])
+
+
+@pytest.mark.parametrize("name,N,nx,ny", [
+    ("D2V37", 4, 70, 13),    # unaligned rows: 256 consecutive nodes per block, ragged tail
+    ("D2V37", 4, 128, 20),   # aligned rows: (x tile, row) grid, per-XCD row bands
+    ("D2V37", 3, 192, 11),   # aligned, three 64-node tiles per row
+    ("D2V17", 3, 2, 5),      # nx < |e_x|
+    ("D2V32", 4, 128, 30),   # halo 12: buffer-addressed row grid
+    ("D2V32", 3, 5, 29),     # halo 12, nx < |e_x|
+])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-14), ("f32", 1e-8), ("f16dev", 1e-4)])
+def test_ping_pong_2d_elementwise(name, N, nx, ny, storage, tol):
+    """The 2D ping-pong step (two copies, each step pulls from one into the
+    other), which the library takes by default above 512 MiB per copy, forced
+    at small sizes: element by element against the oracle after odd and even
+    step counts (FP64 absolute; FP32 and FP16 deviations relative to w)."""
+    rho, u = wl.random_state(nx * ny, 2, seed=nx * 7 + ny, amp=1e-3)
+    d, g, o = make_pair(name, N, nx, ny, kn=0.05, storage=storage, rho=rho, u=u,
+                        layout="ping_pong")
+    w = d.weights[:, None, None]
+    for steps in (1, 6, 9):
+        g.run(steps)
+        o.run(steps)
+        pg, po = populations_both(d, g, o)
+        err = np.abs(pg - po) if storage == "f64" else np.abs(pg - po) / w
+        assert np.max(err) <= tol, steps
+    og, oo = g.observe(), o.observe()
+    bar = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3}[storage]
+    assert abs(og["mdot"] - oo["mdot"]) <= bar * abs(oo["mdot"])
+
+
+def test_ping_pong_and_in_place_agree_bitwise():
+    """Both layouts perform the same arithmetic per node: a random D2V37 state
+    stepped 25 times in place and ping-pong gives identical populations, for
+    FP64, FP32 and FP16 deviations (whose stochastic rounding keys on node and
+    step, not on the layout)."""
+    nx, ny = 128, 24
+    rho, u = wl.random_state(nx * ny, 2, seed=44, amp=1e-2)
+    for storage in ("f64", "f32", "f16dev"):
+        _, a, _ = make_pair("D2V37", 4, nx, ny, storage=storage, rho=rho, u=u, layout="in_place")
+        _, b, _ = make_pair("D2V37", 4, nx, ny, storage=storage, rho=rho, u=u, layout="ping_pong")
+        a.run(25)
+        b.run(25)
+        assert torch.equal(a.export(), b.export()), storage
+
+
+def _full_size_ping_pong(nx, ny, storage, steps, tol, seed):
+    from paper_1510_08886_amd import lbm
+    d0 = lbm.Dvm.named("D2V37")
+    copy = 37 * nx * ny * {"f64": 8, "f32": 4, "f16dev": 2}[storage]
+    pop, _ = lbm.state_bytes(d0, lbm.Problem(dim=2, nx=nx, ny=ny, kn=0.05, hermite_order=4,
+                                              storage=storage))
+    # above 512 MiB per copy: two copies (ping-pong); above 1 GiB for the pair:
+    # streaming stores
+    assert copy > 512 << 20 and pop == 2 * copy and pop > 1 << 30
+    rho = wl.density_field(ny, nx, seed=seed, amp=1e-3)
+    d, g, o = make_pair("D2V37", 4, nx, ny, kn=0.05, ma=1e-3, storage=storage, rho=rho)
+    w = d.weights[:, None, None]
+    for _ in range(steps):
+        g.run(1)
+        o.run(1, nthreads=min(16, os.cpu_count() or 1))
+        pg, po = populations_both(d, g, o)
+        err = np.abs(pg - po) if storage == "f64" else np.abs(pg - po) / w
+        assert np.max(err) <= tol
+        del pg, po
+    og, oo = g.observe(), o.observe()
+    bar = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3}[storage]
+    assert abs(og["mdot"] - oo["mdot"]) <= bar * abs(oo["mdot"])
+    mass_bar = {"f64": 1e-12, "f32": 1e-8, "f16dev": 1e-6}[storage]
+    assert abs(og["mass"] - oo["mass"]) <= mass_bar * oo["mass"]
+
+
+def test_full_size_ping_pong_f64_2048x1024():
+    """D2V37 FP64 2048 x 1024: 620 MB per copy, so the default layout is two
+    copies stepped ping-pong with streaming stores. Two steps over the whole
+    grid against the oracle to 1e-14."""
+    _full_size_ping_pong(2048, 1024, "f64", 2, 1e-14, seed=1024)
+
+
+def test_full_size_ping_pong_f32_4096x1024():
+    """D2V37 FP32 4096 x 1024 (620 MB per copy, 1.24 GB for the pair): the
+    default ping-pong step with streaming stores, one step over the whole grid
+    against the oracle to 1e-6 of w."""
+    _full_size_ping_pong(4096, 1024, "f32", 1, 1e-6, seed=4096)
+
+
+def test_full_size_ping_pong_f16dev_4096x2048():
+    """D2V37 FP16 deviations 4096 x 2048 (620 MB per copy): the buffer-addressed
+    ping-pong step with streaming stores and stochastic rounding, one step over
+    the whole grid against the oracle to 1e-5 of w."""
+    _full_size_ping_pong(4096, 2048, "f16dev", 1, 1e-5, seed=2048)
+
+
+@pytest.mark.parametrize("name,N,nx,ny,band_rows", [
+    ("D2V37", 4, 128, 20, 0),    # aligned rows, default bands
+    ("D2V37", 4, 70, 13, 0),     # partial second strip (6 columns), unaligned
+    ("D2V37", 4, 130, 24, 5),    # bands of 5 rows: halos reach across several bands
+    ("D2V37", 3, 64, 64, 1),     # one-row bands
+    ("D2V17", 3, 2, 5, 0),       # nx < |e_x|: the widened tile repeats columns
+    ("D2V17", 3, 1, 21, 2),      # streamwise-invariant column, two-row bands
+    ("D2V37", 5, 192, 11, 3),    # Hermite order 5; every band touches a wall
+    ("D2V33", 5, 96, 17, 7),     # halo 4
+    ("D2V16", 4, 64, 9, 0),      # halo 4, no rest velocity, ny < 2 * halo
+])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f32raw"])
+def test_pair_steps_equal_single_steps(name, N, nx, ny, band_rows, storage):
+    """Two steps per launch (the intermediate state in an LDS ring) against one
+    launch per step: bit-identical populations after even and odd step counts
+    (an odd count ends with one single step), on random states, for every
+    storage; FP64 also element by element against the oracle."""
+    rho, u = wl.random_state(nx * ny, 2, seed=nx * 3 + ny, amp=1e-2)
+    d, a, o = make_pair(name, N, nx, ny, kn=0.07, ma=2e-2, storage=storage, rho=rho, u=u,
+                        layout="ping_pong")
+    _, b, _ = make_pair(name, N, nx, ny, kn=0.07, ma=2e-2, storage=storage, rho=rho, u=u,
+                        layout="ping_pong")
+    a.set_graph_steps(0).set_pair_steps(True, band_rows)
+    b.set_graph_steps(0).set_pair_steps(False)
+    for steps in (2, 7, 4):
+        a.run(steps)
+        b.run(steps)
+        assert torch.equal(a.export(), b.export()), steps
+        if storage == "f64":
+            o.run(steps)
+            pg, po = populations_both(d, a, o)
+            assert np.max(np.abs(pg - po)) <= 1e-14, steps
+    ma, mb = a.observe(), b.observe()
+    assert ma["mdot"] == mb["mdot"] and ma["mass"] == mb["mass"]
+
+
+def test_pair_steps_full_size_channel():
+    """The 2048 x 512 D2V37 FP32 throughput channel stepped ping-pong with two
+    steps per launch (default bands: one per XCD): 10 steps bit-identical to
+    single-step launches, then two more against the oracle over the grid."""
+    c = wl.THROUGHPUT_D2V37
+    rho = wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"])
+    d, a, o = make_pair(c["dvm"], c["N"], c["nx"], c["ny"], kn=c["kn"], ma=c["ma"],
+                        storage="f32", rho=rho, layout="ping_pong")
+    _, b, _ = make_pair(c["dvm"], c["N"], c["nx"], c["ny"], kn=c["kn"], ma=c["ma"],
+                        storage="f32", rho=rho, layout="ping_pong")
+    a.set_pair_steps(True)
+    b.set_pair_steps(False)
+    a.run(10)
+    b.run(10)
+    assert torch.equal(a.export(), b.export())
+    o.run(10, nthreads=min(16, os.cpu_count() or 1))
+    a.run(2)
+    o.run(2, nthreads=min(16, os.cpu_count() or 1))
+    pg, po = populations_both(d, a, o)
+    assert np.max(np.abs(pg - po) / d.weights[:, None, None]) <= 1e-6
