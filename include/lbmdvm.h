@@ -198,6 +198,7 @@ int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop
                       lbm_solver_t **out);
 int lbm_solver_destroy(lbm_solver_t *s);
 
+
 /* Set the post-collision state to the equilibrium f^(0)(rho, u) of Eq.
  * equi.hermite at every node. rho_dev[nodes] and u_dev[nodes * 3] are device
  * FP64 arrays in node order ((k * ny + j) * nx + i); NULL means rho0 and rest. */
@@ -225,8 +226,12 @@ int lbm_solver_set_resident_steps(lbm_solver_t *s, int max_steps);
  * is read and written in HBM once per two lattice updates. The arithmetic and
  * results are bit for bit those of one launch per step. on = 0 switches it
  * off; band_rows is the height of each workgroup's band of rows (0: chosen
- * for the device). Compiled for the 2D sets reaching at most 4 nodes; off by
- * default; LBM_E_UNSUPPORTED for on != 0 elsewhere. lbm_run takes two-step
+ * for the device). on = 1 alternates the two steps in all waves of a
+ * workgroup; on = 2 gives them to producer and consumer waves that overlap.
+ * Compiled for the 2D sets reaching at most 4 nodes. Default 2 for
+ * ping-pong problems that are not graph-replayed, in FP64 and FP32 storage;
+ * 0 otherwise (FP16 deviations: their single step is bound by its arithmetic).
+ * LBM_E_UNSUPPORTED for on != 0 where not compiled. lbm_run takes two-step
  * launches while two or more steps remain. */
 int lbm_solver_set_pair_steps(lbm_solver_t *s, int on, int band_rows);
 

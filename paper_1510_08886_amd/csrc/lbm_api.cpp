@@ -167,7 +167,8 @@ struct Solver {
     int layout = kLocal;            // PopLayout of pop
     double *apart[2] = {nullptr, nullptr};
     double *partial = nullptr;
-    double *out = nullptr;
+    double *out = nullptr;          // two doubles of observation results, then the error word
+    int *err = nullptr;             // set by a kernel whose bounded wait gave up
     double *invd = nullptr;
     std::vector<double> invd_host;  // source of the asynchronous upload of invd
     int cur = 0;
@@ -187,10 +188,11 @@ struct Solver {
     std::vector<Graph> graphs;
     hipStream_t capture = nullptr;
     int graph_steps = 0;
+    bool graphs_allowed = true;     // false for solvers that may not own runtime memory
     // Most steps per one-workgroup resident launch (0: off; see lbm_run).
     int resident_steps = 0;
     // Two ping-pong steps per launch (Launch::pair) and its band height (0: auto).
-    bool pair_steps = false;
+    int pair_steps = 0;             // 0 off, 1 one workgroup per CU, 2 two per CU
     int pair_band_rows = 0;
     ~Solver() {
         if (!graphs.empty() || capture) (void)hipStreamSynchronize(stream);
@@ -395,12 +397,14 @@ extern "C" int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, 
     return LBM_OK;
 }
 
-extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
-                                 void *pop_b, void *scratch, size_t scratch_bytes, void *stream,
-                                 lbm_solver_t **out) {
+// A solver over the caller's population buffer and a scratch buffer (the
+// caller's, or the library's static one). Graph replay (captured graphs own
+// runtime memory) only when `graphs`.
+int lbm::solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
+                       void *scratch, size_t scratch_bytes, void *stream, bool graphs,
+                       lbm_solver_t **out) {
     if (!out) return fail(LBM_E_INVALID, "lbm_solver_create: null output");
     *out = nullptr;
-    (void)pop_b;  // the update runs in place: one population array
     if (!dvm || !prob || !pop_a || !scratch)
         return fail(LBM_E_INVALID, "lbm_solver_create: null argument");
     const Dvm &d = *reinterpret_cast<const Dvm *>(dvm);
@@ -431,30 +435,52 @@ extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob
     s->invd = (double *)(base + L.off_invd);
     s->partial = (double *)(base + L.off_partial);
     s->out = (double *)(base + L.off_out);
+    s->err = (int *)(base + L.off_out + 2 * sizeof(double));
     s->stream = (hipStream_t)stream;
     s->nodes = nodes_of(*prob);
-    s->graph_steps = (st != Storage::F16DEV && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
+    s->graph_steps =
+        (graphs && st != Storage::F16DEV && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
+    s->graphs_allowed = graphs;
     s->resident_steps = resident_ok(*s) ? kResidentMaxSteps : 0;
     // two steps per launch where compiled, for ping-pong problems not already
     // stepped from graphs
-    s->pair_steps = false;
+    // two steps per launch for ping-pong problems not stepped from graphs,
+    // producer and consumer waves (mode 2). Measured on MI355X, D2V37 FP32
+    // 4096 x 2048 (1.24 GB per copy): 303 us per step against 437 us for one
+    // launch per step. FP16 deviations keep single steps: their step is
+    // bound by its arithmetic (252 against 319 us).
+    s->pair_steps = (pair_ok(*s) && s->graph_steps == 0 && st != Storage::F16DEV) ? 2 : 0;
     if (st == Storage::F64)
         fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
     else
         fill_tables<float>(d, *prob, s->par, s->tab, s->sc);
-    // zero the wall partials so a run before init is well defined
-    hipError_t e = hipMemsetAsync(scratch, 0, L.off_partial, s->stream);
-    if (e == hipSuccess && prob->dim == 3) {
+    // zero the wall partials so a run before init is well defined, and the
+    // error word
+    rc = launch_zero(scratch, L.off_partial, s->stream);
+    if (rc == LBM_OK) rc = launch_zero(s->out, L.scratch_bytes - L.off_out, s->stream);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    hipError_t e = hipSuccess;
+    if (prob->dim == 3) {
         duct_invd(d, *prob, s->par, s->invd_host);
         e = hipMemcpyAsync(s->invd, s->invd_host.data(), sizeof(double) * s->invd_host.size(),
                            hipMemcpyHostToDevice, s->stream);
     }
     if (e != hipSuccess) {
         delete s;
-        return fail(LBM_E_DEVICE, std::string("memset: ") + hipGetErrorString(e));
+        return fail(LBM_E_DEVICE, std::string("1/D(e) upload: ") + hipGetErrorString(e));
     }
     *out = reinterpret_cast<lbm_solver_t *>(s);
     return LBM_OK;
+}
+
+extern "C" int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
+                                 void *pop_b, void *scratch, size_t scratch_bytes, void *stream,
+                                 lbm_solver_t **out) {
+    (void)pop_b;  // pop_a holds both copies when the problem is stepped ping-pong
+    return solver_create(dvm, prob, pop_a, scratch, scratch_bytes, stream, true, out);
 }
 
 extern "C" int lbm_solver_destroy(lbm_solver_t *h) {
@@ -557,8 +583,10 @@ extern "C" int lbm_run(lbm_solver_t *h, int64_t nsteps) {
             continue;
         }
         if (s.pair_steps && left >= 2) {
-            StepBuffers b{s.pop, s.pop_other, s.layout, s.apart[s.cur], s.apart[1 - s.cur], s.invd};
-            int rc = s.L->pair(b, s.tab, s.sc, s.stream, (uint32_t)s.steps, s.pair_band_rows);
+            StepBuffers b{s.pop,  s.pop_other, s.layout, s.apart[s.cur], s.apart[1 - s.cur],
+                          s.invd, s.err};
+            int rc = s.L->pair(b, s.tab, s.sc, s.stream, (uint32_t)s.steps, s.pair_band_rows,
+                               s.pair_steps);
             if (rc) return rc;
             s.cur ^= 1;
             std::swap(s.pop, s.pop_other);
@@ -594,12 +622,13 @@ extern "C" int lbm_solver_set_resident_steps(lbm_solver_t *h, int max_steps) {
 }
 
 extern "C" int lbm_solver_set_pair_steps(lbm_solver_t *h, int on, int band_rows) {
-    if (!h || band_rows < 0) return fail(LBM_E_INVALID, "lbm_solver_set_pair_steps: bad arguments");
+    if (!h || band_rows < 0 || on < 0 || on > 2)
+        return fail(LBM_E_INVALID, "lbm_solver_set_pair_steps: bad arguments");
     Solver &s = *reinterpret_cast<Solver *>(h);
     if (on && !pair_ok(s))
         return fail(LBM_E_UNSUPPORTED,
                     "two steps per launch: 2D ping-pong problems of a set with a compiled kernel");
-    s.pair_steps = on != 0;
+    s.pair_steps = on;
     s.pair_band_rows = band_rows;
     return LBM_OK;
 }
@@ -609,6 +638,8 @@ extern "C" int lbm_solver_set_graph_steps(lbm_solver_t *h, int max_steps) {
     Solver &s = *reinterpret_cast<Solver *>(h);
     if (max_steps > 0 && s.st == Storage::F16DEV)
         return fail(LBM_E_UNSUPPORTED, "graph replay: FP16 stochastic rounding keys on the step");
+    if (max_steps > 0 && !s.graphs_allowed)
+        return fail(LBM_E_UNSUPPORTED, "graph replay: this solver allocates nothing (static scratch)");
     s.graph_steps = std::min(max_steps, 4096);
     return LBM_OK;
 }
@@ -620,11 +651,14 @@ static int observe_impl(Solver &s, double *rho_dev, double *u_dev, double *mdot,
     if (!mdot && !mass) return LBM_OK;
     rc = launch_finalize(s.partial, observe_blocks(s.nodes), s.out, s.stream);
     if (rc) return rc;
-    double host[2];
+    double host[4];   // the two results, then the error word
     hipError_t e = hipMemcpyAsync(host, s.out, sizeof(host), hipMemcpyDeviceToHost, s.stream);
     if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("copy: ") + hipGetErrorString(e));
     rc = sync_check(s.stream);
     if (rc) return rc;
+    int err = 0;
+    std::memcpy(&err, &host[2], sizeof(err));
+    if (err) return fail(LBM_E_DEVICE, "a two-step launch gave up waiting: the state is invalid");
     if (mdot) *mdot = s.par.mdot_scale * host[0] / (double)s.nodes;
     if (mass) *mass = host[1];
     return LBM_OK;

@@ -90,6 +90,7 @@ struct StepBuffers {
     const double *a_cur;            // wall-flux partials of the current state [face][halo][elements]
     double *a_next;                 // wall-flux partials written by the step
     const double *invd;             // 3D: 1 / D(e) per face and position along it
+    int *err;                       // set by a kernel whose bounded wait gave up (or null)
 };
 
 // Launchers (instantiated in the .hip translation units).
@@ -112,7 +113,7 @@ struct Launch {
     // -> a_next): the intermediate state stays on chip (null where not
     // compiled). band_rows = rows per workgroup band (0: chosen for the chip).
     int (*pair)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, uint32_t step,
-                int band_rows);
+                int band_rows, int mode);
 };
 
 // Channel stencils reaching at least this far (max |e_i|, the set's halo) use
@@ -140,9 +141,17 @@ int match_set(const Dvm &d);
 // Returns nullptr when no kernel is compiled for this combination.
 const Launch *find_launch(int set_id, Storage s);
 
+// Zero `bytes` (a multiple of 4) of device memory at p with a kernel.
+int launch_zero(void *p, size_t bytes, hipStream_t st);
+
 // Sum of `n` doubles laid out as partials[n][2] into out[2] in a fixed order.
 int launch_finalize(const double *partials, int n, double *out, hipStream_t st);
 
 int observe_blocks(int64_t nodes);
+
+// lbm_solver_create over any scratch buffer; graph replay only when `graphs`
+// (captured graphs own runtime memory).
+int solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a, void *scratch,
+                  size_t scratch_bytes, void *stream, bool graphs, lbm_solver_t **out);
 
 }  // namespace lbm

@@ -315,40 +315,76 @@ __global__ __launch_bounds__(256) void k_run2d(StepBuffers b, PairTable<typename
 // that wall's rows in step t (its widened rows reach them), so every wall row
 // of step t + 1 finds its column's partials.
 // ---------------------------------------------------------------------------
-template <class SET, typename T>
+// Two schedules, both one workgroup per CU (the ring takes most of the LDS):
+//   kPairAlternate: all waves compute step t of a chunk of RR rows, a barrier,
+//     then all compute step t + 1 of the chunk (ring of RR + 2 HN rows);
+//   kPairSplit: producer waves compute step t of chunk k + 1 while consumer
+//     waves compute step t + 1 of chunk k (ring of 2 RR + 2 HN rows), so the
+//     HBM reads of one overlap the arithmetic of the other. The two groups
+//     hand over chunks through two LDS counters (release / acquire at
+//     workgroup scope); a workgroup's waves are resident together, so every
+//     wait ends. Each wait is also bounded: one that gives up raises a flag in
+//     device memory (read by the host at the next observation) and its wave
+//     leaves, and so, in turn, does the other group's.
+enum PairKind : int { kPairAlternate = 1, kPairSplit = 2 };
+
+template <class SET, typename T, int KIND>
 struct PairTile {
     static constexpr int H = SET::H, HN = SET::HN, V = SET::V;
-    static constexpr size_t kLds = 156 * 1024;   // of the 160 KB of a gfx950 CU
+    static constexpr size_t kLds = 156 * 1024;     // of the 160 KB of a gfx950 CU
+    // ring rows for chunks of rr rows
+    static constexpr int ring_rows(int rr) { return (KIND == kPairSplit ? 2 : 1) * rr + 2 * HN; }
     static constexpr size_t bytes(int bx, int rr) {
-        return (size_t)(rr + 2 * HN) * (bx + 2 * H) * V * sizeof(T) + (size_t)2 * HN * bx * 8;
+        return (size_t)ring_rows(rr) * (bx + 2 * H) * V * sizeof(T) + (size_t)2 * HN * bx * 8;
     }
-    static constexpr int pick_bx() { return bytes(64, 8) <= kLds ? 64 : 32; }
+    static constexpr int up64(int x) { return (x + 63) / 64 * 64; }
+    // threads: one step-t node of a chunk each (split: plus one step-(t+1)
+    // node of a chunk each, in waves of their own)
+    static constexpr int threads(int bx, int rr) {
+        return up64(rr * (bx + 2 * H)) + (KIND == kPairSplit ? up64(rr * bx) : 0);
+    }
+    static constexpr bool fits(int bx, int rr) { return bytes(bx, rr) <= kLds && threads(bx, rr) <= 1024; }
+    static constexpr int pick_bx() { return fits(64, KIND == kPairSplit ? 4 : 8) ? 64 : 32; }
     static constexpr int pick_rr(int bx) {
-        return bytes(bx, 16) <= kLds && 16 * (bx + 2 * H) <= 1024 ? 16
-               : bytes(bx, 8) <= kLds                                      ? 8
-               : bytes(bx, 4) <= kLds                                      ? 4
-                                                                           : 2;
+        return fits(bx, 16) ? 16 : fits(bx, 8) ? 8 : fits(bx, 6) ? 6 : fits(bx, 4) ? 4 : 2;
     }
     static constexpr int BX = pick_bx();
     static constexpr int RR = pick_rr(BX);
     static constexpr int EW = BX + 2 * H;          // ring row pitch (columns)
-    static constexpr int RING = RR + 2 * HN;       // ring rows
-    static constexpr bool ok = bytes(BX, RR) <= kLds && H <= 4;
-    // threads: one step-t node of a chunk each
-    static constexpr int NT = ((RR * EW + 63) / 64) * 64 > 1024 ? 1024 : ((RR * EW + 63) / 64) * 64;
+    static constexpr int RING = ring_rows(RR);
+    static constexpr bool ok = fits(BX, RR) && H <= 4;
+    static constexpr int PT = up64(RR * EW);
+    static constexpr int CT = KIND == kPairSplit ? up64(RR * BX) : 0;
+    static constexpr int NT = PT + CT;
 };
 
-template <class SET, Storage S, bool ALIGNED, bool STREAM, bool N5>
-__global__ __launch_bounds__((PairTile<SET, typename St<S>::T>::NT))
+// bound of one wait on the other group (~0.5 s): only a broken schedule reaches it
+constexpr uint32_t kPairSpinLimit = 1u << 23;
+
+__device__ __forceinline__ bool pair_wait(const int *cnt, int target, int *err) {
+    for (uint32_t k = 0;; ++k) {
+        if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target)
+            return true;
+        if (k >= kPairSpinLimit) {
+            if (err) *err = 1;
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <class SET, Storage S, bool ALIGNED, bool STREAM, bool N5, int KIND>
+__global__ __launch_bounds__((PairTile<SET, typename St<S>::T, KIND>::NT))
 void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typename St<S>::R> s,
               uint32_t step, int band_rows) {
     using R = typename St<S>::R;
     using T = typename St<S>::T;
-    using TL = PairTile<SET, T>;
+    using TL = PairTile<SET, T, KIND>;
     constexpr int H = SET::H, HN = SET::HN, V = SET::V, NR = SET::NR;
     constexpr int BX = TL::BX, RR = TL::RR, EW = TL::EW, RING = TL::RING;
     __shared__ T ring[RING * V * EW];      // [row mod RING][alpha][column]
     __shared__ double ap[2 * HN * BX];     // step-t partials of the tile's columns [face][row][col]
+    __shared__ int produced, consumed;     // kPairSplit: waves done per group, summed over chunks
 
     // tile of this workgroup: XCD x (workgroups go to the 8 XCDs round-robin)
     // takes a contiguous run of tiles in (band, strip) order, so the strips
@@ -361,15 +397,22 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     const int x0 = strip * BX, ncols = min(BX, nx - x0);
     const int y0 = band * band_rows, y1 = min(y0 + band_rows, ny);
     const int a = max(y0 - HN, 0);         // first step-t row of the band
-    const T *A = (const T *)b.pop;
-    const GlobalPop<T> src{const_cast<T *>(A)};
+    const GlobalPop<T> src{(T *)b.pop};
     const GlobalPop<T> dst{(T *)b.pop_out};
 
-    // step t of rows [lo, hi), columns x0 - H .. x0 + ncols + H - 1, into the ring
-    auto first = [&](int lo, int hi) {
+    // ring slot of row `row` given the slot sl0 of row r0, |row - r0| < RING
+    auto slot_from = [](int sl0, int r0, int row) {
+        int x = sl0 + (row - r0);
+        x = x < 0 ? x + RING : x;
+        return x >= RING ? x - RING : x;
+    };
+    // step t of rows [lo, hi), columns x0 - H .. x0 + ncols + H - 1, into the
+    // ring; threads tid, tid + nth, ...
+    auto first = [&](int lo, int hi, int tid, int nth) {
         const int w = ncols + 2 * H;
         const int n1 = (hi - lo) * w;
-        for (int e = threadIdx.x; e < n1; e += blockDim.x) {
+        const int sl = (lo - a) % RING;
+        for (int e = tid; e < n1; e += nth) {
             const int rl = e / w, c = e - rl * w;
             const int j = lo + rl;
             const int i = wrap_col(x0 - H + c, nx, H);
@@ -384,31 +427,37 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
             relax2d<SET, R, N5>(d, t, s, t.c);
             T v[V];
             encode_all<SET, S, true>(d, t, n, step, v);
-            T *rw = ring + (size_t)((j - a) % RING) * (V * EW) + c;
+            T *rw = ring + slot_from(sl, lo, j) * (V * EW) + c;
 #pragma unroll
             for (int q = 0; q < V; ++q) rw[q * EW] = v[q];
             if (c >= H && c < H + ncols) wall_partials2d_col<SET, S>(v, t, s, j, ap + (c - H), BX);
         }
     };
     // step t + 1 of rows [lo, hi), the tile's own columns, from the ring to HBM
-    auto second = [&](int lo, int hi) {
+    auto second = [&](int lo, int hi, int tid, int nth) {
         const int n2 = (hi - lo) * BX;
-        for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+        const int sl = (lo - a) % RING;
+        for (int e = tid; e < n2; e += nth) {
             const int rl = e / BX, il = e - rl * BX;
             if (il >= ncols) continue;
             const int j = lo + rl, i = x0 + il;
             const uint32_t n = (uint32_t)j * (uint32_t)nx + (uint32_t)i;
-            auto at = [&](int row, int slot, int col) -> T {
-                const int jr = min(max(row, 0), ny - 1);
-                return ring[(size_t)((jr - a) % RING) * (V * EW) + slot * EW + col];
-            };
+            // ring position of column il + H in the rows j - k, clamped into
+            // the channel as the HBM pull clamps them (a wall slot reads a
+            // valid value that complete2d_col replaces)
+            const T *rb[2 * HN + 1];
+#pragma unroll
+            for (int k = -HN; k <= HN; ++k) {
+                const int jr = min(max(j - k, 0), ny - 1);
+                rb[k + HN] = ring + slot_from(sl, lo, jr) * (V * EW) + il + H;
+            }
             T raw[V];
-            if constexpr (NR) raw[0] = at(j, 0, il + H);
+            if constexpr (NR) raw[0] = rb[HN][0];
             for_pairs<SET::NP>([&](auto pc) {
                 constexpr int p = decltype(pc)::value;
                 constexpr int ex = SET::EX[p], ey = SET::EY[p];
-                raw[NR + 2 * p] = at(j - ey, NR + 2 * p, il + H - ex);
-                raw[NR + 2 * p + 1] = at(j + ey, NR + 2 * p + 1, il + H + ex);
+                raw[NR + 2 * p] = rb[ey + HN][(NR + 2 * p) * EW - ex];
+                raw[NR + 2 * p + 1] = rb[HN - ey][(NR + 2 * p + 1) * EW + ex];
             });
             R d[V];
             complete2d_col<SET, S>(raw, ap + il, BX, t, s, j, d);
@@ -419,16 +468,48 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
             wall_partials2d<SET, S>(v, t, s, i, j, b.a_next);
         }
     };
+    // step-t rows chunk k needs: [a, need(k))
+    auto need = [&](int k) { return min(y0 + (k + 1) * RR + HN, min(y1 + HN, ny)); };
+    const int chunks = (y1 - y0 + RR - 1) / RR;
 
-    int ready = a;   // step-t rows [a, ready) are in the ring
-    for (int lo = y0; lo < y1; lo += RR) {
-        const int hi = min(lo + RR, y1);
-        const int need = min(hi + HN, ny);
-        first(ready, need);
-        ready = need;
+    if constexpr (KIND == kPairAlternate) {
+        for (int k = 0; k < chunks; ++k) {
+            first(k == 0 ? a : need(k - 1), need(k), threadIdx.x, blockDim.x);
+            __syncthreads();
+            second(y0 + k * RR, min(y0 + (k + 1) * RR, y1), threadIdx.x, blockDim.x);
+            __syncthreads();
+        }
+    } else {
+        static_assert(TL::PT + TL::CT <= 1024, "producer and consumer waves fit one workgroup");
+        constexpr int PW = TL::PT / 64, CW = TL::CT / 64;
+        if (threadIdx.x == 0) {
+            produced = 0;
+            consumed = 0;
+        }
         __syncthreads();
-        second(lo, hi);
-        __syncthreads();
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        // A wave counts chunk k only once every wave of its group has counted
+        // chunk k - 1, so produced >= PW (k + 1) means that all producer
+        // waves have finished chunk k (a fast wave cannot stand in for a slow
+        // one), and likewise for consumed.
+        if (wave < PW) {
+            // producer: chunk k overwrites the ring rows of chunk k - 2
+            for (int k = 0; k < chunks; ++k) {
+                if (k >= 2 && !pair_wait(&consumed, CW * (k - 1), b.err)) return;
+                first(k == 0 ? a : need(k - 1), need(k), threadIdx.x, TL::PT);
+                if (!pair_wait(&produced, PW * k, b.err)) return;
+                if (lane == 0)
+                    __hip_atomic_fetch_add(&produced, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            for (int k = 0; k < chunks; ++k) {
+                if (!pair_wait(&produced, PW * (k + 1), b.err)) return;
+                second(y0 + k * RR, min(y0 + (k + 1) * RR, y1), threadIdx.x - TL::PT, TL::CT);
+                if (!pair_wait(&consumed, CW * k, b.err)) return;
+                if (lane == 0)
+                    __hip_atomic_fetch_add(&consumed, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
     }
 }
 
@@ -659,18 +740,15 @@ struct L2 {
         return hip_ok(hipGetLastError(), "resident step kernel launch");
     }
     // Two steps per launch (k_pair2d). Bands: the fewest that give every CU
-    // at least one workgroup, so that the rows recomputed at band edges stay
-    // few; a forced band height (tests, tuning) may be anything >= 1.
-    static int pair(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
-                    uint32_t stp, int band_rows) {
-        using TL = PairTile<SET, typename St<S>::T>;
+    // a workgroup, so that the rows recomputed at band edges stay few; a
+    // forced band height (tests, tuning) may be anything >= 1.
+    template <int KIND>
+    static int pair_launch(const StepBuffers &b, const PairTable<R> &t, const StepScalars<R> &s,
+                           hipStream_t st, uint32_t stp, int band_rows) {
+        using TL = PairTile<SET, typename St<S>::T, KIND>;
         if constexpr (!TL::ok) {
             return fail(LBM_E_UNSUPPORTED, "two-step kernel: stencil too wide for the LDS ring");
         } else {
-            const auto &t = *(const PairTable<R> *)tab;
-            const auto &s = *(const StepScalars<R> *)sc;
-            if (b.layout != kDirect || !b.pop_out)
-                return fail(LBM_E_INVALID, "two-step kernel: needs two population copies");
             const int nstrips = (s.nx + TL::BX - 1) / TL::BX;
             if (band_rows <= 0) {
                 int dev = 0, cus = 256;
@@ -684,8 +762,9 @@ struct L2 {
             const dim3 g((unsigned)(nstrips * bands)), bl(TL::NT);
             bool n5 = false;
             if constexpr (SET::Q >= 9) n5 = s.cn[5] != R(0);
-#define LBM_PAIR(AL, STR, N5V) \
-    hipLaunchKernelGGL((k_pair2d<SET, S, AL, STR, N5V>), g, bl, 0, st, b, t, s, stp, band_rows)
+#define LBM_PAIR(AL, STR, N5V)                                                                  \
+    hipLaunchKernelGGL((k_pair2d<SET, S, AL, STR, N5V, KIND>), g, bl, 0, st, b, t, s, stp, \
+                       band_rows)
             const bool al = s.nx % 64 == 0, str = s.stream_stores != 0;
             if (n5) {
                 if constexpr (SET::Q >= 9) {
@@ -702,9 +781,20 @@ struct L2 {
             return hip_ok(hipGetLastError(), "two-step kernel launch");
         }
     }
+    // mode 1: alternating phases; mode 2: producer and consumer waves
+    static int pair(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
+                    uint32_t stp, int band_rows, int mode) {
+        const auto &t = *(const PairTable<R> *)tab;
+        const auto &s = *(const StepScalars<R> *)sc;
+        if (b.layout != kDirect || !b.pop_out)
+            return fail(LBM_E_INVALID, "two-step kernel: needs two population copies");
+        return mode == 2 ? pair_launch<kPairSplit>(b, t, s, st, stp, band_rows)
+                         : pair_launch<kPairAlternate>(b, t, s, st, stp, band_rows);
+    }
     static constexpr Launch table{&step,    &init,         &observe, &exportp,
                                   &importp, &run_resident,
-                                  PairTile<SET, typename St<S>::T>::ok ? &pair : nullptr};
+                                  PairTile<SET, typename St<S>::T, kPairAlternate>::ok ? &pair
+                                                                                    : nullptr};
 };
 
 #define LBM_2D(SET)                                                           \

@@ -2,6 +2,8 @@
 // of observation sums.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbm_device.h"
 
 namespace lbm {
@@ -33,6 +35,24 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partial, int n, 
         out[0] = sa[0];
         out[1] = sb[0];
     }
+}
+
+// zero fill of a device buffer (used instead of hipMemsetAsync so that the
+// launch may also be recorded in a captured graph)
+__global__ __launch_bounds__(256) void k_zero(uint32_t *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+int launch_zero(void *p, size_t bytes, hipStream_t st) {
+    if (bytes % 4 != 0 || (uintptr_t)p % 4 != 0)
+        return fail(LBM_E_INVALID, "zero fill: 4-byte aligned buffers and sizes only");
+    const size_t n = bytes / 4;
+    if (n == 0) return LBM_OK;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (uint32_t *)p, n);
+    return hip_ok(hipGetLastError(), "zero kernel launch");
 }
 
 int launch_finalize(const double *partials, int n, double *out, hipStream_t st) {

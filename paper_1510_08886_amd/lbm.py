@@ -16,6 +16,7 @@ PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "liblbmdvm.so"
 
 LBM_OK = 0
+LBM_E_UNSUPPORTED = -2
 ERRORS = {-1: "LBM_E_INVALID", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_NO_MEMORY",
           -4: "LBM_E_QUADRATURE", -5: "LBM_E_DEVICE", -6: "LBM_E_NOT_CONVERGED"}
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "f32raw": 3}
@@ -315,12 +316,12 @@ class Solver:
         self.dvm, self.prob = dvm, prob
         self.device = torch.device(device)
         pop_b, scr_b = state_bytes(dvm, prob)
-        # 256-byte aligned allocations from torch's allocator; one population
-        # array (the library updates it in place)
+        # 256-byte aligned allocations from torch's allocator: the population
+        # buffer (one copy stepped in place, or two ping-pong) and the scratch
         self.pop = torch.empty(pop_b, dtype=torch.uint8, device=self.device)
         self.scratch = torch.empty(scr_b, dtype=torch.uint8, device=self.device)
         for t in (self.pop, self.scratch):
-            if t.data_ptr() % 256:
+            if t is not None and t.data_ptr() % 256:
                 raise RuntimeError("device allocation is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = params(dvm, prob)
@@ -355,10 +356,11 @@ class Solver:
               "lbm_solver_set_resident_steps")
         return self
 
-    def set_pair_steps(self, on: bool, band_rows: int = 0):
+    def set_pair_steps(self, on, band_rows: int = 0):
         """Two time steps per launch (2D ping-pong problems; bitwise the same
-        results); band_rows 0 lets the library choose."""
-        check(lib().lbm_solver_set_pair_steps(self._h, int(bool(on)), int(band_rows)),
+        results): on = False/0 off, True/1 one workgroup per CU, 2 two per CU;
+        band_rows 0 lets the library choose."""
+        check(lib().lbm_solver_set_pair_steps(self._h, int(on), int(band_rows)),
               "lbm_solver_set_pair_steps")
         return self
 
