@@ -198,6 +198,22 @@ int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop
                       lbm_solver_t **out);
 int lbm_solver_destroy(lbm_solver_t *s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid
+ * hipMalloc): lbm_solver_create without a scratch argument. The scratch lives
+ * in a static device array of the library (16 MiB; each device the library
+ * runs on holds its own copy until the process ends), and the solver never
+ * replays captured graphs (lbm_solver_set_graph_steps then returns
+ * LBM_E_UNSUPPORTED), so neither this call nor any later call on the solver
+ * allocates device or pinned memory; the handle itself is an ordinary host
+ * object. The caller still provides pop_a (lbm_state_bytes) and the stream.
+ * LBM_E_NO_MEMORY if the problem needs more than 16 MiB of scratch (its
+ * *scratch_bytes from lbm_state_bytes). Every static solver on one device
+ * shares that device's array, and creation clears it: at most one static
+ * solver per device may be in use at a time; solvers that overlap on one
+ * device race. */
+int lbm_solver_create_static(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
+                             void *stream, lbm_solver_t **out);
 
 /* Set the post-collision state to the equilibrium f^(0)(rho, u) of Eq.
  * equi.hermite at every node. rho_dev[nodes] and u_dev[nodes * 3] are device

@@ -16,7 +16,7 @@ BUILD_DIR = ROOT / "_build"
 
 SOURCES = ["lbm_kernels.hip", "lbm_kernels3d.hip", "lbm_batch.hip", "lbm_registry.hip", "lbm_api.cpp",
            "lbm_dvm.cpp", "lbm_wall.cpp",
-           "lbm_profile.cpp", "lbm_measure.hip"]
+           "lbm_profile.cpp", "lbm_measure.hip", "lbm_static.hip"]
 
 # gfx950 only; packed FP32 instructions are switched off for all device code.
 # Multiply-adds are fused only within a source expression (-ffp-contract=on),

@@ -102,6 +102,7 @@ SIGNATURES = {
     "lbm_solver_create": ([_P, ctypes.POINTER(ProblemC), _P, _P, _P, ctypes.c_size_t, _P,
                            ctypes.POINTER(_P)], _I),
     "lbm_solver_destroy": ([_P], _I),
+    "lbm_solver_create_static": ([_P, ctypes.POINTER(ProblemC), _P, _P, ctypes.POINTER(_P)], _I),
     "lbm_init_equilibrium": ([_P, _P, _P], _I),
     "lbm_run": ([_P, _I64], _I),
     "lbm_run_to_tol": ([_P, _D, _I, _I64, ctypes.POINTER(_I64), _DP], _I),
@@ -309,7 +310,11 @@ def _ptr(t) -> int:
 class Solver:
     """One channel / duct solve on caller-owned torch device buffers."""
 
-    def __init__(self, dvm: Dvm, prob: Problem, device: str = "cuda", stream=None):
+    def __init__(self, dvm: Dvm, prob: Problem, device: str = "cuda", stream=None,
+                 static_scratch: bool = False):
+        """static_scratch: the library's static device scratch
+        (lbm_solver_create_static) instead of a torch-allocated one; at most
+        one such solver per device may be in use at a time."""
         import torch
 
         self.torch = torch
@@ -319,7 +324,8 @@ class Solver:
         # 256-byte aligned allocations from torch's allocator: the population
         # buffer (one copy stepped in place, or two ping-pong) and the scratch
         self.pop = torch.empty(pop_b, dtype=torch.uint8, device=self.device)
-        self.scratch = torch.empty(scr_b, dtype=torch.uint8, device=self.device)
+        self.scratch = (None if static_scratch
+                        else torch.empty(scr_b, dtype=torch.uint8, device=self.device))
         for t in (self.pop, self.scratch):
             if t is not None and t.data_ptr() % 256:
                 raise RuntimeError("device allocation is not 256-byte aligned")
@@ -329,10 +335,17 @@ class Solver:
         self.shape = ((prob.nz, prob.ny, prob.nx) if prob.dim == 3 else (prob.ny, prob.nx))
         pc = prob.to_c()
         h = _P()
-        check(lib().lbm_solver_create(dvm._h, ctypes.byref(pc), _ptr(self.pop), None,
-                                      _ptr(self.scratch), scr_b,
-                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-              "lbm_solver_create")
+        if static_scratch:
+            check(lib().lbm_solver_create_static(dvm._h, ctypes.byref(pc), _ptr(self.pop),
+                                                 ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(h)),
+                  "lbm_solver_create_static")
+        else:
+            check(lib().lbm_solver_create(dvm._h, ctypes.byref(pc), _ptr(self.pop), None,
+                                          _ptr(self.scratch), scr_b,
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)),
+                  "lbm_solver_create")
         self._h = h
 
     def init(self, rho=None, u=None):
