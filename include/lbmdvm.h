@@ -78,7 +78,11 @@ typedef struct {
     int g_set;            /* 1: take g[] as given */
     double g[3];          /* body-force acceleration (Eq. nm.4); g.n must be 0 */
     int hermite_order;    /* N of the equilibrium (Eq. equi.hermite), 2..(Q+1)/2 */
-    double accommodation; /* 1 = fully diffuse Maxwell wall (only value supported) */
+    double accommodation; /* Maxwell's accommodation alpha in [0, 1]: the fraction of
+                             the populations reaching a wall that is re-emitted
+                             diffusely (the paper's wall is alpha = 1); the rest is
+                             reflected specularly. alpha < 1: 2D channels only,
+                             stepped ping-pong (LBM_LAYOUT_IN_PLACE is refused) */
     double rho0;          /* reference density (deviation storage, initial state) */
     int storage;          /* enum lbm_storage */
     int layout;           /* enum lbm_layout: how the populations are kept in HBM */
@@ -190,9 +194,10 @@ int lbm_state_bytes(const lbm_dvm_t *dvm, const lbm_problem_t *prob, size_t *pop
  * layouts); otherwise pop_a holds two copies, stepped ping-pong. pop_b is not
  * used and may be NULL.
  * Validation (LBM_E_INVALID): ny (and nz in 3D) >= the largest |e_n|;
- * 2 <= N <= (Q+1)/2; kn > 0; g.n = 0; sizes positive. accommodation != 1 gives
- * LBM_E_UNSUPPORTED, as do N > 5 and a velocity set without a compiled kernel
- * (N = 5 is compiled for the sets of quadrature order 9). */
+ * 2 <= N <= (Q+1)/2; kn > 0; g.n = 0; sizes positive; 0 <= accommodation
+ * <= 1. accommodation < 1 for a duct gives LBM_E_UNSUPPORTED, as do N > 5 and
+ * a velocity set without a compiled kernel (N = 5 is compiled for the sets of
+ * quadrature order 9). */
 int lbm_solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *pop_a,
                       void *pop_b, void *scratch, size_t scratch_bytes, void *stream,
                       lbm_solver_t **out);
@@ -334,8 +339,8 @@ int lbm_batch_create(int max_slots, int storage, void *pool, size_t pool_bytes, 
 int lbm_batch_destroy(lbm_batch_t *b);
 
 /* Queue one channel solve: prob->dim = 2, prob->nx = 1, prob->storage equal
- * to the batch's, Hermite order N <= 4 (else LBM_E_UNSUPPORTED); the DVM must
- * be D2V17 or D2V37. It runs from the rest
+ * to the batch's, Hermite order N <= 4 and accommodation 1 (else
+ * LBM_E_UNSUPPORTED); the DVM must be D2V17 or D2V37. It runs from the rest
  * state rho0 w until |mdot_k - mdot_{k-1}| < tol |mdot_k| with mdot evaluated
  * every check_every steps, or until max_steps. LBM_E_NO_MEMORY if it can
  * never fit the pool or the LDS of one workgroup. */

@@ -31,6 +31,13 @@
  *     the weight |n.xi|; on the lattice a population with |e_n| = m crosses
  *     from m rows). A wall element is the cell of the fluid node next to the
  *     crossing, on the face crossed first going outward from that node.
+ *   - Maxwell's accommodation alpha < 1 (not treated in the paper, which
+ *     takes the fully diffuse wall; channel walls normal to y only): the
+ *     diffuse part re-emits alpha times the absorbed populations as above,
+ *     and a fraction 1 - alpha is reflected specularly, i.e. with the wall
+ *     normal velocity component reversed. The specular partner of the slot
+ *     (x, alpha) is the population with the reflected velocity that leaves
+ *     from the image of the virtual source x - e_alpha in the wall plane.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -52,6 +59,7 @@ typedef struct {
     double tau;       /* relaxation time */
     double dt;        /* time step */
     double g[3];      /* body-force acceleration */
+    double alpha;     /* accommodation: diffuse fraction of the wall (1 in the paper) */
 } orc_problem;
 
 enum { FACE_YLO = 0, FACE_YHI = 1, FACE_ZLO = 2, FACE_ZHI = 3 };
@@ -228,6 +236,16 @@ int orc_wall_balance(const orc_problem *p, const double *fpost, double *A, doubl
     return 0;
 }
 
+/* Index of the velocity (e_x, -e_y, e_z) of velocity a. */
+static int reflected_y(const orc_problem *p, int a)
+{
+    for (int b = 0; b < p->V; ++b)
+        if (p->e[3 * b] == p->e[3 * a] && p->e[3 * b + 1] == -p->e[3 * a + 1] &&
+            p->e[3 * b + 2] == p->e[3 * a + 2])
+            return b;
+    return -1;
+}
+
 /* Streaming pass: fpre(x) = fpost(x - e) inside, wall value otherwise. */
 int orc_stream(const orc_problem *p, const double *fpost, double *fpre)
 {
@@ -252,7 +270,17 @@ int orc_stream(const orc_problem *p, const double *fpost, double *fpre)
                     } else {
                         long el = wall_element(p, i, j, k, -ey, -ez, oy, oz);
                         double rho_eff = Dn[el] > 0.0 ? A[el] / Dn[el] : 0.0;
-                        fpre[n * V + a] = rho_eff * wall_shape(p, a);
+                        double diffuse = rho_eff * wall_shape(p, a);
+                        if (p->alpha == 1.0) {
+                            fpre[n * V + a] = diffuse;
+                        } else {
+                            /* image of the source row in the wall plane
+                             * y = -1/2 (below) or y = ny - 1/2 (above) */
+                            int jm = js < 0 ? -1 - js : 2 * p->ny - 1 - js;
+                            int b = reflected_y(p, a);
+                            double spec = fpost[node_id(p, is, jm, k) * V + b];
+                            fpre[n * V + a] = p->alpha * diffuse + (1.0 - p->alpha) * spec;
+                        }
                     }
                 }
             }

@@ -44,7 +44,7 @@ class _Problem(ctypes.Structure):
                 ("walls_z", ctypes.c_int), ("pad_", ctypes.c_int),
                 ("e", ctypes.POINTER(ctypes.c_int)), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("c", ctypes.c_double), ("tau", ctypes.c_double), ("dt", ctypes.c_double),
-                ("g", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("alpha", ctypes.c_double)]
 
 
 _lib = None
@@ -102,7 +102,13 @@ class OracleSolver:
 
     def __init__(self, dvm, nx: int, ny: int, nz: int = 1, kn: float = 0.1,
                  ma: float | None = 1e-3, N: int = 3, walls_z: bool = False,
-                 g: tuple | None = None):
+                 g: tuple | None = None, alpha: float = 1.0):
+        """alpha: Maxwell accommodation (1 = the paper's fully diffuse wall);
+        below 1 only for channels (walls normal to y)."""
+        if not 0.0 <= alpha <= 1.0:
+            raise ValueError("accommodation must lie in [0, 1]")
+        if alpha != 1.0 and (dvm.dim != 2 or walls_z):
+            raise ValueError("accommodation below 1: channels (walls normal to y) only")
         self.dvm = dvm
         self.dim = dvm.dim
         self.nx, self.ny, self.nz = nx, ny, (nz if dvm.dim == 3 else 1)
@@ -123,6 +129,7 @@ class OracleSolver:
         p.c, p.tau, p.dt = dvm.c, self.params.tau, self.params.dt
         for d in range(3):
             p.g[d] = self.params.g[d]
+        p.alpha = float(alpha)
         self._p = p
         self.nodes = self.nx * self.ny * self.nz
         self.f = np.zeros((self.nodes, V))

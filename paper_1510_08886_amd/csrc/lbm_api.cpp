@@ -72,8 +72,12 @@ Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
     Layout L;
     const int64_t nodes = nodes_of(p);
     L.copy_bytes = align_up((size_t)d.V * plane_of(nodes) * storage_bytes(p.storage));
-    L.in_place = p.layout == LBM_LAYOUT_IN_PLACE ||
-                 (p.layout == LBM_LAYOUT_AUTO && L.copy_bytes <= kInPlaceMaxBytes);
+    // Specular reflection (accommodation < 1) reads another node's leaving
+    // population, which the in-place kernels overwrite in the same step: such
+    // problems step ping-pong.
+    L.in_place = p.accommodation == 1.0 &&
+                 (p.layout == LBM_LAYOUT_IN_PLACE ||
+                  (p.layout == LBM_LAYOUT_AUTO && L.copy_bytes <= kInPlaceMaxBytes));
     L.pop_bytes = L.in_place ? L.copy_bytes : 2 * L.copy_bytes;
     L.apart_bytes = align_up(sizeof(double) * 4 * std::max(1, d.halo) * face_elems(p));
     L.partial_bytes = align_up(sizeof(double) * 2 * observe_blocks(nodes));
@@ -128,8 +132,13 @@ int validate(const Dvm &d, const lbm_problem_t &p) {
     if (p.layout != LBM_LAYOUT_AUTO && p.layout != LBM_LAYOUT_IN_PLACE &&
         p.layout != LBM_LAYOUT_PING_PONG)
         return fail(LBM_E_INVALID, "unknown population layout");
-    if (p.accommodation != 1.0)
-        return fail(LBM_E_UNSUPPORTED, "only the fully diffuse Maxwell wall (accommodation 1) is implemented");
+    if (!(p.accommodation >= 0.0 && p.accommodation <= 1.0))
+        return fail(LBM_E_INVALID, "accommodation must lie in [0, 1]");
+    if (p.accommodation != 1.0 && p.dim != 2)
+        return fail(LBM_E_UNSUPPORTED, "accommodation below 1 is implemented for 2D channels");
+    if (p.accommodation != 1.0 && p.layout == LBM_LAYOUT_IN_PLACE)
+        return fail(LBM_E_UNSUPPORTED,
+                    "accommodation below 1 steps ping-pong (specular partners belong to other nodes)");
     if (d.V / 2 > kMaxPairs) return fail(LBM_E_UNSUPPORTED, "velocity set too large for the kernel tables");
     // kernels index populations and nodes with 32-bit integers
     if ((double)d.V * (double)plane_of(nodes_of(p)) >= 4294967296.0)
@@ -283,6 +292,8 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     }
     for (int k = 0; k < 4; ++k) s->invD[k] = D[k] > 0 ? 1.0 / D[k] : 0.0;
     s->hgc = 0.5 * par.dt * par.g[0] * d.c;
+    s->alpha = p.accommodation;
+    s->specular = p.accommodation < 1.0 ? 1 : 0;
     // w rho0 of the populations that leave through each face from wall row r
     const bool dev_storage = p.storage == LBM_F32 || p.storage == LBM_F16DEV;
     for (int r = 0; r < kMaxWallRows; ++r) {

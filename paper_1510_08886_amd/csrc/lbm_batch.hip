@@ -553,6 +553,8 @@ extern "C" int lbm_batch_submit(lbm_batch_t *h, const lbm_dvm_t *dvm, const lbm_
         return fail(LBM_E_UNSUPPORTED, "lbm_batch_submit: batched solves are 2D channels with nx = 1");
     if (prob->storage != (int)b.st)
         return fail(LBM_E_INVALID, "lbm_batch_submit: storage differs from the batch's");
+    if (prob->accommodation != 1.0)
+        return fail(LBM_E_UNSUPPORTED, "lbm_batch_submit: the batched kernel has fully diffuse walls");
     if (prob->hermite_order > 4)
         return fail(LBM_E_UNSUPPORTED, "lbm_batch_submit: the batched kernel implements Hermite orders up to 4");
     const int set = match_set(d);

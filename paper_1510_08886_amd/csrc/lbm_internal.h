@@ -58,6 +58,8 @@ struct StepScalars {
     double kA[4][kMaxWallRows];     // per face and wall row r: sum of w rho0 over the
                                     // velocities leaving through the face from row r
                                     // (deviation storages; 0 otherwise)
+    double alpha;                   // accommodation: diffuse fraction of the wall (2D)
+    int specular;                   // alpha < 1: the rest is reflected specularly
     int nx, ny, nz, halo;
     int64_t plane;                  // nodes rounded up to whole 64-node blocks
     int aligned_rows;               // nx is a multiple of 64: a row starts a block

@@ -234,7 +234,11 @@ __device__ __forceinline__ void step_node2d(const StepBuffers &b,
         read_pull<SET, KIND == kGatherScatter>(pop, nb, own, raw);
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     R d[SET::V];
-    complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
+    // specular walls (accommodation < 1) are stepped ping-pong only
+    if constexpr (KIND == kPingPong)
+        complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d, ArrayMirror<SET, T>{(const T *)b.pop, i, s.nx});
+    else
+        complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
     relax2d<SET, R, N5>(d, t, s, t.c);
     T v[SET::V];
     encode_all<SET, S, true>(d, t, n, step, v);
@@ -423,7 +427,7 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
                 read_pull<SET, false>(src, nb, Ix{aos_base<V>(n), 0u, 0u}, raw);
             }
             R d[V];
-            complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d);
+            complete2d<SET, S>(raw, b.a_cur, t, s, i, j, d, ArrayMirror<SET, T>{(const T *)b.pop, i, nx});
             relax2d<SET, R, N5>(d, t, s, t.c);
             T v[V];
             encode_all<SET, S, true>(d, t, n, step, v);
@@ -459,8 +463,12 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
                 raw[NR + 2 * p] = rb[ey + HN][(NR + 2 * p) * EW - ex];
                 raw[NR + 2 * p + 1] = rb[HN - ey][(NR + 2 * p + 1) * EW + ex];
             });
+            // specular partners from the ring (rows next to a wall are in it)
+            auto ring_mirror = [&](int slot, int jm, int ex) -> T {
+                return ring[slot_from(sl, lo, jm) * (V * EW) + mirror_slot<SET>(slot) * EW + il + H - ex];
+            };
             R d[V];
-            complete2d_col<SET, S>(raw, ap + il, BX, t, s, j, d);
+            complete2d_col<SET, S>(raw, ap + il, BX, t, s, j, d, ring_mirror);
             relax2d<SET, R, N5>(d, t, s, t.c);
             T v[V];
             encode_all<SET, S, true>(d, t, n, step + 1u, v);
@@ -541,7 +549,8 @@ __global__ __launch_bounds__(256) void k_observe2d(const void *pop, int layout, 
                 read_pull<SET, false>(A, nb, own, raw);
         }
         R d[SET::V];
-        complete2d<SET, S>(raw, a_cur, t, s, i, j, d);
+        // (specular walls only occur in the ping-pong layout, kDirect)
+        complete2d<SET, S>(raw, a_cur, t, s, i, j, d, ArrayMirror<SET, T>{(const T *)pop, i, s.nx});
         const auto m = moments2d<SET, R>(d, s, t.c);
         rho_d = s.rho0d + (double)m.drho;
         ux_d = (double)m.ux;

@@ -123,17 +123,58 @@ __device__ __forceinline__ void relax2d(R (&d)[SET::V], const PairTable<R> &t,
 // ---------------------------------------------------------------------------
 // wall slots and wall-flux partials (2D channel)
 // ---------------------------------------------------------------------------
+// Slot of the velocity (e_x, -e_y) for slot a (reflection at a wall normal to
+// y); the velocity sets are symmetric under it.
+template <class SET>
+constexpr int mirror_slot(int a) {
+    constexpr int NR = SET::NR;
+    if (NR && a == 0) return 0;
+    const int p = (a - NR) / 2;
+    const int sg = (a - NR) % 2 ? -1 : 1;
+    const int ex = sg * SET::EX[p], ey = -sg * SET::EY[p];
+    for (int q = 0; q < SET::NP; ++q) {
+        if (SET::EX[q] == ex && SET::EY[q] == ey) return NR + 2 * q;
+        if (SET::EX[q] == -ex && SET::EY[q] == -ey) return NR + 2 * q + 1;
+    }
+    return -1;
+}
+template <class SET>
+constexpr bool mirror_complete() {
+    for (int a = 0; a < SET::V; ++a)
+        if (mirror_slot<SET>(a) < 0) return false;
+    return true;
+}
+
+// No specular partners (fully diffuse walls).
+template <typename T>
+struct NoMirror {
+    __device__ __forceinline__ T operator()(int, int, int) const { return T(0); }
+};
+
 // raw[] holds the stored values at the (clamped) pull sources; decode them to
 // deviations and replace the values whose source lies outside the channel by
-// the diffuse-wall populations. a_col points at the FP64 partials of the
-// node's column, [face][row < HN] with row stride `stride` (the global
-// partials [face][row][column] have stride nx).
-template <class SET, Storage S>
+// the wall's populations. a_col points at the FP64 partials of the node's
+// column, [face][row < HN] with row stride `stride` (the global partials
+// [face][row][column] have stride nx).
+//
+// Maxwell's wall with accommodation alpha (s.specular when alpha < 1; the
+// paper treats alpha = 1): a fraction alpha of the populations that reach an
+// element is re-emitted diffusely, alpha rho_eff w (1 - dt/2 g.xi), and the
+// rest reflected specularly: the unknown slot (e_x, e_y) of node (i, j) whose
+// source row j - e_y lies beyond a wall receives 1 - alpha times the
+// post-collision population (e_x, -e_y) of the node (i - e_x, jm) mirrored
+// about that wall, jm = -1 - (j - e_y) below and 2 ny - 1 - (j - e_y) above
+// (the straight path from x - e folded at the wall plane). mir(slot, jm, e_x)
+// returns that stored value for the unknown slot `slot` (y-reflected velocity
+// mirror_slot(slot)); it is only called when s.specular.
+template <class SET, Storage S, class MIR = NoMirror<typename St<S>::T>>
 __device__ __forceinline__ void complete2d_col(const typename St<S>::T (&raw)[SET::V],
                                                const double *__restrict__ a_col, int stride,
                                                const PairTable<typename St<S>::R> &t,
                                                const StepScalars<typename St<S>::R> &s, int j,
-                                               typename St<S>::R (&d)[SET::V]) {
+                                               typename St<S>::R (&d)[SET::V],
+                                               const MIR &mir = MIR()) {
+    using T = typename St<S>::T;
     using R = typename St<S>::R;
     constexpr int NR = SET::NR, HN = SET::HN;
     const int ny = s.ny;
@@ -152,6 +193,7 @@ __device__ __forceinline__ void complete2d_col(const typename St<S>::T (&raw)[SE
             ahi += a_col[(HN + r) * stride];
         }
         const double rlo = alo * s.invD[0], rhi = ahi * s.invD[1];
+        static_assert(mirror_complete<SET>(), "velocity set closed under y reflection");
         // wall population w (rho_eff (1 - dt/2 g.xi)) as a deviation from w rho0
         const double rho0 = s.rho0d, hgc = s.hgc;
         for_pairs<SET::NP>([&](auto pc) {
@@ -159,29 +201,59 @@ __device__ __forceinline__ void complete2d_col(const typename St<S>::T (&raw)[SE
             constexpr int ex = SET::EX[p], ey = SET::EY[p];
             if constexpr (ey != 0) {
                 const double wd = (double)t.w[p];
+                constexpr int mp = mirror_slot<SET>(NR + 2 * p), mm = mirror_slot<SET>(NR + 2 * p + 1);
                 int js = j - ey;
                 if (js < 0 || js >= ny) {
                     const double re = js < 0 ? rlo : rhi;
-                    d[NR + 2 * p] = (R)(wd * (re * (1.0 - hgc * ex) - rho0));
+                    double dv = wd * (re * (1.0 - hgc * ex) - rho0);
+                    if (s.specular) {
+                        const int jm = js < 0 ? -1 - js : 2 * ny - 1 - js;
+                        const R sp = decode_dev<S>((T)mir(NR + 2 * p, jm, ex),
+                                                   t.wr0[(mp - NR) / 2]);
+                        dv = s.alpha * dv + (1.0 - s.alpha) * (double)sp;
+                    }
+                    d[NR + 2 * p] = (R)dv;
                 }
                 js = j + ey;
                 if (js < 0 || js >= ny) {
                     const double re = js < 0 ? rlo : rhi;
-                    d[NR + 2 * p + 1] = (R)(wd * (re * (1.0 + hgc * ex) - rho0));
+                    double dv = wd * (re * (1.0 + hgc * ex) - rho0);
+                    if (s.specular) {
+                        const int jm = js < 0 ? -1 - js : 2 * ny - 1 - js;
+                        const R sp = decode_dev<S>((T)mir(NR + 2 * p + 1, jm, -ex),
+                                                   t.wr0[(mm - NR) / 2]);
+                        dv = s.alpha * dv + (1.0 - s.alpha) * (double)sp;
+                    }
+                    d[NR + 2 * p + 1] = (R)dv;
                 }
             }
         });
     }
 }
 
-template <class SET, Storage S>
+template <class SET, Storage S, class MIR = NoMirror<typename St<S>::T>>
 __device__ __forceinline__ void complete2d(const typename St<S>::T (&raw)[SET::V],
                                            const double *__restrict__ a_cur,
                                            const PairTable<typename St<S>::R> &t,
                                            const StepScalars<typename St<S>::R> &s, int i, int j,
-                                           typename St<S>::R (&d)[SET::V]) {
-    complete2d_col<SET, S>(raw, a_cur + i, s.nx, t, s, j, d);
+                                           typename St<S>::R (&d)[SET::V], const MIR &mir = MIR()) {
+    complete2d_col<SET, S>(raw, a_cur + i, s.nx, t, s, j, d, mir);
 }
+
+// Specular partner in a kDirect AoSoA-64 population array (node n at
+// aos_base(n), velocity alpha in slot alpha) that the step does not write:
+// specular walls are stepped ping-pong only, since in the in-place layouts the
+// mirrored node overwrites that population in the same step.
+template <class SET, typename T>
+struct ArrayMirror {
+    const T *A;
+    int i, nx;
+    __device__ __forceinline__ T operator()(int slot, int jm, int ex) const {
+        const int col = wrap_col(i - ex, nx, SET::H);
+        const int at = mirror_slot<SET>(slot);
+        return A[aos_base<SET::V>((uint32_t)jm * (uint32_t)nx + (uint32_t)col) + 64u * (uint32_t)at];
+    }
+};
 
 // FP64 partial, per wall row and column, of the just-stored populations that
 // leave through each face in the next streaming step (plus the constant

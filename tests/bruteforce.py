@@ -34,8 +34,21 @@ def force(w, xi, rho, u, g, Pi):
     return rho * w * (t + s / (2.0 * rho))
 
 
-def step(f, vels, weights, c, nx, ny, N, tau, dt, g):
-    """One stream + collide step of a 2D channel with walls at y (half-way)."""
+def _fold(y, ny):
+    """Cell-unit coordinate y (walls at 0 and ny) folded back into the channel
+    by reflection in the wall it crossed."""
+    if y < 0:
+        return -y
+    if y > ny:
+        return 2 * ny - y
+    return y
+
+
+def step(f, vels, weights, c, nx, ny, N, tau, dt, g, alpha=1.0):
+    """One stream + collide step of a 2D channel with walls at y (half-way).
+    alpha: Maxwell accommodation; the fraction 1 - alpha of each wall value is
+    the specularly reflected population, found by following the arriving
+    particle back over one step and folding its path at the wall."""
     ws = dict(zip(vels, weights))
 
     def shape(e):
@@ -64,7 +77,14 @@ def step(f, vels, weights, c, nx, ny, N, tau, dt, g):
                     pre[(i, j, e)] = f[((i - e[0]) % nx, js, e)]
                 else:
                     key = (0 if js < 0 else 1, i)
-                    pre[(i, j, e)] = A.get(key, 0.0) / Dn[key] * shape(e)
+                    val = A.get(key, 0.0) / Dn[key] * shape(e)
+                    if alpha != 1.0:
+                        # start of the folded path: cell centre j + 1/2 moved
+                        # back by e_y, reflected in the wall, velocity reversed
+                        yc = _fold(j + 0.5 - e[1], ny)
+                        src = ((i - e[0]) % nx, int(round(yc - 0.5)), (e[0], -e[1]))
+                        val = alpha * val + (1.0 - alpha) * f[src]
+                    pre[(i, j, e)] = val
     out = {}
     omega = dt / (tau + 0.5 * dt)
     h = dt / (2.0 * tau)

@@ -37,16 +37,16 @@ def dvm_pair(name):
 
 
 def make_pair(name, N, nx, ny, nz=1, kn=0.1, ma=1e-3, storage="f64", rho=None, u=None,
-              walls_z=False, layout="auto"):
+              walls_z=False, layout="auto", alpha=1.0):
     import torch
     from paper_1510_08886_amd import lbm
 
     d, od = dvm_pair(name)
     prob = lbm.Problem(dim=d.dim, nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, hermite_order=N,
-                       storage=storage, layout=layout)
+                       storage=storage, layout=layout, accommodation=alpha)
     g = lbm.Solver(d, prob)
     o = stepper.OracleSolver(od, nx=nx, ny=ny, nz=nz, kn=kn, ma=ma, N=N,
-                             walls_z=walls_z or d.dim == 3)
+                             walls_z=walls_z or d.dim == 3, alpha=alpha)
     if rho is None:
         g.init()
         o.init()

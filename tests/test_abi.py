@@ -89,15 +89,50 @@ def test_params_match_paper_relations():
 
 @pytest.mark.parametrize("field,value,code", [
     ("ny", 2, -1), ("hermite_order", 1, -1), ("hermite_order", 5, -1), ("kn", 0.0, -1),
-    ("g", (1e-3, 1e-4), -1), ("accommodation", 0.5, -2), ("rho0", 0.0, -1), ("nx", 0, -1),
+    ("g", (1e-3, 1e-4), -1), ("accommodation", 1.5, -1), ("accommodation", -0.1, -1),
+    ("rho0", 0.0, -1), ("nx", 0, -1), ("layout", "other", None),
 ])
 def test_validation_errors(field, value, code):
     d = lbm.Dvm.named("D2V17")
     prob = lbm.Problem(dim=2, nx=4, ny=10, kn=0.1, hermite_order=3)
     setattr(prob, field, value)
+    if code is None:     # rejected by the binding before the library
+        with pytest.raises(KeyError):
+            lbm.state_bytes(d, prob)
+        return
     with pytest.raises(lbm.LbmError) as e:
         lbm.state_bytes(d, prob)
     assert e.value.code == code
+
+
+def test_accommodation_below_one_is_2d_only():
+    """Maxwell accommodation alpha < 1 (specular reflection of the rest) is
+    implemented for channels; ducts and the batched engine refuse it."""
+    d2 = lbm.Dvm.named("D2V17")
+    lbm.state_bytes(d2, lbm.Problem(dim=2, nx=4, ny=10, kn=0.1, hermite_order=3,
+                                    accommodation=0.5))
+    d3 = lbm.Dvm.named("D3V39")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.state_bytes(d3, lbm.Problem(dim=3, nx=4, ny=10, nz=10, kn=0.1, hermite_order=3,
+                                        accommodation=0.5))
+    assert e.value.code == -2
+    # specular partners belong to other nodes: ping-pong only (two copies)
+    prob = lbm.Problem(dim=2, nx=4, ny=10, kn=0.1, hermite_order=3, accommodation=0.5)
+    assert lbm.state_bytes(d2, prob)[0] == 2 * lbm.state_bytes(
+        d2, lbm.Problem(dim=2, nx=4, ny=10, kn=0.1, hermite_order=3))[0]
+    prob.layout = "in_place"
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.state_bytes(d2, prob)
+    assert e.value.code == -2
+
+
+def test_layout_choice_sets_copies():
+    d = lbm.Dvm.named("D2V37")
+    base = dict(dim=2, nx=128, ny=20, kn=0.05, hermite_order=4, storage="f32")
+    one = 37 * 128 * 20 * 4
+    assert lbm.state_bytes(d, lbm.Problem(**base))[0] == one
+    assert lbm.state_bytes(d, lbm.Problem(**base, layout="in_place"))[0] == one
+    assert lbm.state_bytes(d, lbm.Problem(**base, layout="ping_pong"))[0] == 2 * one
 
 
 def test_state_bytes_layout():

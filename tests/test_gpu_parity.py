@@ -429,3 +429,79 @@ def test_pair_steps_full_size_channel():
     o.run(2, nthreads=min(16, os.cpu_count() or 1))
     pg, po = populations_both(d, a, o)
     assert np.max(np.abs(pg - po) / d.weights[:, None, None]) <= 1e-6
+
+
+@pytest.mark.parametrize("name,N,nx,ny", [
+    ("D2V37", 4, 70, 13),    # unaligned rows, ragged tail
+    ("D2V37", 4, 128, 20),   # aligned rows, both in-place kinds on the row grid
+    ("D2V17", 3, 2, 5),      # nx < |e_x|: mirrored sources wrap in x
+    ("D2V33", 5, 64, 9),     # halo 4, order-5 equilibrium
+    ("D2V32", 4, 128, 30),   # halo 12, buffer-addressed row grid
+    ("D2V32", 3, 5, 29),     # halo 12, nx < |e_x|
+    ("D2V37", 4, 1, 21),     # one column: in place this is the one-workgroup resident kernel
+])
+@pytest.mark.parametrize("layout", ["auto", "ping_pong"])
+@pytest.mark.parametrize("alpha", [0.0, 0.3, 0.75])
+def test_accommodation_elementwise(name, N, nx, ny, layout, alpha):
+    """Maxwell walls with a diffuse fraction alpha and the rest reflected
+    specularly, FP64 (such problems step ping-pong: the specular partner is
+    another node's leaving population, which the in-place kernels overwrite in
+    the same step), element by element against the oracle, then the observed
+    moments (which read the specular partners too)."""
+    rho, u = wl.random_state(nx * ny, 2, seed=nx * 5 + ny, amp=2e-2)
+    d, g, o = make_pair(name, N, nx, ny, kn=0.07, ma=2e-2, rho=rho, u=u, layout=layout,
+                        alpha=alpha)
+    for steps in (1, 6, 9):
+        g.run(steps)
+        o.run(steps)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po)) <= 1e-14, steps
+    og, oo = g.observe(), o.observe()
+    np.testing.assert_allclose(og["rho"].cpu().numpy(), oo["rho"], rtol=1e-14)
+    np.testing.assert_allclose(og["u"].cpu().numpy()[..., :2], oo["u"][..., :2], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("storage,tol_pop", [("f32", 1e-8), ("f16dev", 1e-4)])
+def test_accommodation_low_precision(storage, tol_pop):
+    nx, ny = 128, 24
+    rho, u = wl.random_state(nx * ny, 2, seed=61, amp=1e-3)
+    d, g, o = make_pair("D2V37", 4, nx, ny, kn=0.05, storage=storage, rho=rho, u=u,
+                        alpha=0.6)
+    w = d.weights[:, None, None]
+    for steps in (1, 40, 59):
+        g.run(steps)
+        o.run(steps)
+        pg, po = populations_both(d, g, o)
+        assert np.max(np.abs(pg - po) / w) <= tol_pop, steps
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_accommodation_pair_steps(mode, storage):
+    """Two steps per launch with specular partners taken from the LDS ring
+    (second step) and from HBM (first step): bitwise equal to single steps."""
+    nx, ny = 130, 24
+    rho, u = wl.random_state(nx * ny, 2, seed=62, amp=1e-2)
+    _, a, _ = make_pair("D2V37", 4, nx, ny, storage=storage, rho=rho, u=u, layout="ping_pong",
+                        alpha=0.45)
+    _, b, _ = make_pair("D2V37", 4, nx, ny, storage=storage, rho=rho, u=u, layout="ping_pong",
+                        alpha=0.45)
+    a.set_graph_steps(0).set_pair_steps(mode, 5)
+    b.set_graph_steps(0).set_pair_steps(False)
+    for steps in (2, 7, 4):
+        a.run(steps)
+        b.run(steps)
+        assert torch.equal(a.export(), b.export()), steps
+
+
+def test_specular_channel_accelerates_freely():
+    """alpha = 0 from rest (D2V37 FP64, 64 x 7): u_x = (n + 1/2) g dt at every
+    node after n steps, u_y = 0 (the plug flow of fully specular walls)."""
+    d, g, _ = make_pair("D2V37", 4, 64, 7, kn=0.2, alpha=0.0)
+    par = g.params
+    g.run(33)
+    o = g.observe()
+    ux = o["u"][..., 0].cpu().numpy()
+    want = 33.5 * par.g[0] * par.dt
+    assert np.max(np.abs(ux - want)) <= 1e-12 * want
+    assert np.max(np.abs(o["u"][..., 1].cpu().numpy())) <= 1e-16
