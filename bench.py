@@ -112,6 +112,50 @@ def cpu_baseline(budget_s: float = 15.0):
             "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
+def throughput_parity(d, prob):
+    """The headline workload run untimed for exactly its 1000 steps from the
+    seeded density, against the stored FP64 oracle run of the same channel
+    (tests/golden/throughput_d2v37.txt, written by a script that calls only the
+    oracle): relative error of the mass flow (Eq. pf.1), of the row-averaged
+    u_x and of rho, u_x, u_y on the stored columns (relative to each field's
+    largest magnitude)."""
+    import numpy as np
+    import torch
+
+    from paper_1510_08886_amd import lbm
+
+    c = wl.THROUGHPUT_D2V37
+    g = {"uxrow": {}, "col": {}}
+    for line in (ROOT / "tests" / "golden" / "throughput_d2v37.txt").read_text().splitlines():
+        t = line.split()
+        if not t or t[0].startswith("#"):
+            continue
+        if t[0] == "mdot" and int(t[1]) == c["steps"]:
+            g["mdot"] = float(t[2])
+        elif t[0] == "uxrow":
+            g["uxrow"][int(t[1])] = float(t[2])
+        elif t[0] == "col":
+            g["col"][(int(t[1]), int(t[2]))] = [float(x) for x in t[3:6]]
+    s = lbm.Solver(d, prob, device="cuda:0")
+    s.init(torch.from_numpy(wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"])))
+    s.run(c["steps"])
+    ob = s.observe()
+    s.close()
+    u, r = ob["u"].cpu().numpy(), ob["rho"].cpu().numpy()
+    want_row = np.array([g["uxrow"][j] for j in range(c["ny"])])
+    row_err = float(np.max(np.abs(u[..., 0].mean(axis=1) - want_row)) / np.max(np.abs(want_row)))
+    field_err = 0.0
+    for i in sorted({i for i, _ in g["col"]}):
+        ref = np.array([g["col"][(i, j)] for j in range(c["ny"])])
+        field_err = max(field_err, float(np.max(np.abs(r[:, i] - ref[:, 0]) / ref[:, 0])))
+        for k in (1, 2):
+            field_err = max(field_err, float(np.max(np.abs(u[:, i, k - 1] - ref[:, k]))
+                                             / np.max(np.abs(ref[:, k]))))
+    return {"steps": c["steps"], "mdot": ob["mdot"], "oracle_mdot": g["mdot"],
+            "mdot_rel_err_vs_oracle": abs(ob["mdot"] - g["mdot"]) / abs(g["mdot"]),
+            "ux_row_rel_err": row_err, "sampled_fields_rel_err": field_err}
+
+
 def copy_gbs(nbytes: int, reps: int = 10) -> float:
     """Bandwidth of the library's plain streaming copy (one 16-byte vector per
     thread, non-temporal stores) of nbytes each way, alternating direction
@@ -483,6 +527,8 @@ def main():
     bytes_per_launch = 2 * d.V * 4 * nodes         # each population read once, written once
     achieved = bytes_per_launch / (ms * 1e-3 / args.steps) / 1e9
     obs = s.observe()
+    s.close()
+    parity = throughput_parity(d, prob)
     out = {
         "metric": "MLUPS (fused stream+collide, D2V37 FP32 channel) & % HBM peak",
         "value": round(mlups, 1),
@@ -507,8 +553,8 @@ def main():
                              "256 MB last-level cache; see above_llc for a 1.24 GB copy"},
         "wall_s": round(wall, 3),
         "mdot_after": obs["mdot"],
+        "parity_vs_oracle": parity,
     }
-    s.close()
     cg = copy_gbs(bytes_per_launch // 2)
     out["measured_copy"] = {"bytes_each_way": bytes_per_launch // 2, "gbs": round(cg, 1),
                             "step_frac_of_copy": round(achieved / cg, 4),

@@ -114,6 +114,37 @@ const char *lbm_last_error(void);
 int lbm_dvm_solve(int dim, int n_groups, const int32_t *gen, int Q, double c_lo,
                   double c_hi, double *c_out, double *w_group_out, int *n_vel_out);
 
+/* One minimal DVM found by lbm_dvm_enumerate. */
+#define LBM_MAX_GROUPS 16
+typedef struct {
+    int dim;
+    int V;                               /* velocities */
+    int E;                               /* stencil energy (1/2c^2) sum |xi|^2 = (1/2) sum |e|^2 */
+    int n_groups;
+    int32_t gen[LBM_MAX_GROUPS * 3];     /* generators, dim entries each: 0 <= g_1 <= ... <= g_dim */
+    double c;                            /* lattice speed c* */
+    double w_group[LBM_MAX_GROUPS];      /* weight of one velocity of each group */
+} lbm_dvm_model_t;
+
+/* All minimal DVMs of dimension dim and quadrature order Q whose stencil
+ * energy is at most e_max (Section II.B, Eqs. dimker and Ssymbol; Table
+ * tab:dvmSummary). A stencil is a set of distinct velocity groups (orbits of
+ * integer generators under signed permutations) with one weight per group
+ * (Eq. wdach); it is a minimal DVM at c* when the moment conditions to degree
+ * Q have exactly one solution there (the orbit moment matrix has full column
+ * rank) and none for c near c*, with all weights positive. Stencils of at
+ * most max_groups groups are searched (0: one less than the number of moment
+ * conditions, the most a minimal DVM can have); c* in [0.02, 50]. flags:
+ * LBM_ENUM_SCATTERING keeps only scattering stencils (no velocity with a zero
+ * component, so none parallel to a wall; Section IV.C). Models are
+ * sorted by V, then E, then c; integer multiples of a stencil appear as
+ * separate models (with c* divided by the factor). out[cap] (host) receives the
+ * first cap models and *n_out the total count; LBM_E_NO_MEMORY when the total
+ * exceeds cap (query with cap = 0). Host only. */
+#define LBM_ENUM_SCATTERING 1
+int lbm_dvm_enumerate(int dim, int Q, int e_max, int max_groups, int flags, lbm_dvm_model_t *out,
+                      int cap, int *n_out);
+
 /* Expand the groups into a velocity set with weights w_group (host arrays) and
  * lattice speed c, and check that it integrates every monomial of degree <= Q
  * exactly (relative tolerance 1e-12 against the Gaussian moment); otherwise

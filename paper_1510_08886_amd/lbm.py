@@ -67,6 +67,15 @@ class WallReportC(ctypes.Structure):
                 ("lambda_index", ctypes.c_uint64), ("sigma_sigma", ctypes.c_double)]
 
 
+MAX_GROUPS = 16
+
+
+class DvmModelC(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("V", ctypes.c_int), ("E", ctypes.c_int),
+                ("n_groups", ctypes.c_int), ("gen", ctypes.c_int32 * (MAX_GROUPS * 3)),
+                ("c", ctypes.c_double), ("w_group", ctypes.c_double * MAX_GROUPS)]
+
+
 class ProfileStatsC(ctypes.Structure):
     _fields_ = [("u_center", ctypes.c_double), ("u_wall", ctypes.c_double),
                 ("slip", ctypes.c_double), ("mean", ctypes.c_double)]
@@ -123,6 +132,7 @@ SIGNATURES = {
     "lbm_batch_autotune": ([_P, _I, _IP], _I),
     "lbm_batch_stats": ([_P, ctypes.POINTER(BatchStatsC)], _I),
     "lbm_stream_copy": ([_P, _P, ctypes.c_size_t, _P], _I),
+    "lbm_dvm_enumerate": ([_I, _I, _I, _I, _I, _P, _I, _IP], _I),
 }
 
 
@@ -286,6 +296,27 @@ class Problem:
         p.storage = STORAGE[self.storage]
         p.layout = LAYOUT[self.layout]
         return p
+
+
+def enumerate_dvms(dim: int, Q: int, e_max: int, max_groups: int = 0,
+                   scattering: bool = False) -> list:
+    """All minimal DVMs of quadrature order Q with stencil energy <= e_max
+    (lbm_dvm_enumerate), sorted by V, E and c: dicts with V, E, c, the
+    generators and the group weights. scattering keeps stencils without a
+    velocity that has a zero component."""
+    flags = 1 if scattering else 0
+    n = ctypes.c_int()
+    rc = lib().lbm_dvm_enumerate(dim, Q, e_max, max_groups, flags, None, 0, ctypes.byref(n))
+    if rc not in (LBM_OK, -3):
+        check(rc, "lbm_dvm_enumerate")
+    buf = (DvmModelC * max(1, n.value))()
+    check(lib().lbm_dvm_enumerate(dim, Q, e_max, max_groups, flags, buf, n.value, ctypes.byref(n)),
+          "lbm_dvm_enumerate")
+    out = []
+    for m in buf[: n.value]:
+        gens = [tuple(m.gen[g * dim + k] for k in range(dim)) for g in range(m.n_groups)]
+        out.append(dict(V=m.V, E=m.E, c=m.c, gens=gens, weights=list(m.w_group[: m.n_groups])))
+    return out
 
 
 def params(dvm: Dvm, prob: Problem) -> ParamsC:

@@ -505,3 +505,62 @@ def test_specular_channel_accelerates_freely():
     want = 33.5 * par.g[0] * par.dt
     assert np.max(np.abs(ux - want)) <= 1e-12 * want
     assert np.max(np.abs(o["u"][..., 1].cpu().numpy())) <= 1e-16
+
+
+def _throughput_golden():
+    from pathlib import Path
+    rows = [l.split() for l in (Path(__file__).resolve().parent / "golden" / "throughput_d2v37.txt")
+            .read_text().splitlines() if l and not l.startswith("#")]
+    g = {"mdot": {}, "uxrow": {}, "col": {}}
+    for r in rows:
+        if r[0] == "mdot":
+            g["mdot"][int(r[1])] = (float(r[2]), float(r[3]))
+        elif r[0] == "uxrow":
+            g["uxrow"][int(r[1])] = float(r[2])
+        elif r[0] == "col":
+            g["col"][(int(r[1]), int(r[2]))] = tuple(float(x) for x in r[3:6])
+        elif r[0] == "steps":
+            g["steps"] = int(r[1])
+    return g
+
+
+@pytest.mark.parametrize("layout,pair", [("auto", 0), ("ping_pong", 2)])
+def test_throughput_channel_1000_steps_against_oracle(layout, pair):
+    """The 2048 x 512 D2V37 FP32 throughput channel, 1000 steps from the seeded
+    density, against the stored FP64 oracle run (tests/golden/throughput_d2v37.txt):
+    the mass flow every 100 steps and the row-averaged u_x within 1e-5
+    relative, and rho, u_x, u_y on four sampled columns within 1e-5 of their
+    largest magnitude (rho elementwise). Default in-place stepping, and
+    ping-pong with two steps per launch."""
+    c = wl.THROUGHPUT_D2V37
+    g = _throughput_golden()
+    rho = wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"])
+    from paper_1510_08886_amd import lbm
+    d = lbm.Dvm.named(c["dvm"])
+    prob = lbm.Problem(dim=2, nx=c["nx"], ny=c["ny"], kn=c["kn"], ma=c["ma"], hermite_order=c["N"],
+                       storage="f32", layout=layout)
+    s = lbm.Solver(d, prob)
+    s.init(torch.from_numpy(rho))
+    if pair:
+        s.set_pair_steps(pair)
+    done = 0
+    for step in sorted(g["mdot"]):
+        s.run(step - done)
+        done = step
+        ob = s.observe()
+        want_md, want_mass = g["mdot"][step]
+        assert abs(ob["mdot"] - want_md) <= 1e-5 * abs(want_md), step
+        assert abs(ob["mass"] - want_mass) <= 1e-9 * want_mass, step
+    assert done == g["steps"] == c["steps"]
+    u = ob["u"].cpu().numpy()
+    r = ob["rho"].cpu().numpy()
+    ux_row = u[..., 0].mean(axis=1)
+    want_row = np.array([g["uxrow"][j] for j in range(c["ny"])])
+    assert np.max(np.abs(ux_row - want_row)) <= 1e-5 * np.max(np.abs(want_row))
+    cols = sorted({i for i, _ in g["col"]})
+    for i in cols:
+        ref = np.array([g["col"][(i, j)] for j in range(c["ny"])])
+        np.testing.assert_allclose(r[:, i], ref[:, 0], rtol=1e-5, atol=0)
+        for k in (1, 2):
+            assert np.max(np.abs(u[:, i, k - 1] - ref[:, k])) <= 1e-5 * np.max(np.abs(ref[:, k])), (i, k)
+    s.close()
