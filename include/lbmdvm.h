@@ -356,6 +356,9 @@ typedef struct {
     int done;          /* finished, not yet returned by poll */
     int threads;       /* workgroup size in use */
     int quantum;       /* steps per launch in the served mode */
+    int slots_per_cu;  /* persistent mode: resident workgroups per CU (LDS permitting) */
+    int order;         /* persistent mode: work-queue order (LBM_BATCH_*) */
+    int64_t graph_replays; /* persistent runs that replayed a captured graph */
     int64_t launches;  /* kernel launches so far */
     size_t pool_used;  /* state bytes allocated */
     size_t pool_free;
@@ -388,18 +391,40 @@ int lbm_batch_poll(lbm_batch_t *b, lbm_result_t *out, int cap, int *n_out);
 int lbm_batch_drain(lbm_batch_t *b, lbm_result_t *out, int cap, int *n_out);
 
 /* Batch mode, blocking: admit every queued request (they must all fit), then
- * run them in ONE persistent launch captured in a HIP graph: workgroups take
- * channels from a device work queue (longest estimated first) and step each to
- * its tolerance. */
+ * run them in ONE persistent launch: workgroups take channels from a device
+ * work queue (longest estimated first) and step each to its tolerance. The
+ * launch is captured in a HIP graph the first time a launch shape (channel
+ * count, grid, workgroup size, LDS) occurs and replayed from then on (at most
+ * 8 graphs per batch, released by lbm_batch_destroy). */
 int lbm_batch_run_persistent(lbm_batch_t *b, lbm_result_t *out, int cap, int *n_out);
 
-/* Workgroup size (64..1024, multiple of 64) and steps per served launch. */
-int lbm_batch_tune(lbm_batch_t *b, int threads, int quantum);
+/* Work-queue orders of persistent launches. */
+#define LBM_BATCH_LONGEST_FIRST 1  /* largest estimated work ny^2 c / tau first (default) */
+#define LBM_BATCH_SUBMIT_ORDER 2   /* order of submission */
 
-/* Time short trial launches of the queued requests for each candidate
- * workgroup size, keep the fastest (results are identical for every choice).
- * The queued requests stay queued. */
-int lbm_batch_autotune(lbm_batch_t *b, int trial_steps, int *threads_out);
+/* Workgroup size (64..1024, multiple of 64; a channel of ny rows takes
+ * ceil(ny / threads) <= 2 rows per thread), steps per served launch,
+ * resident workgroups per CU of persistent launches (1..16) and their
+ * work-queue order (LBM_BATCH_*); 0 keeps the current slots_per_cu / order.
+ * LBM_E_INVALID if a queued or resident channel has more than twice
+ * `threads` rows. */
+int lbm_batch_tune(lbm_batch_t *b, int threads, int quantum, int slots_per_cu, int order);
+
+typedef struct {
+    int threads;       /* chosen workgroup size */
+    int slots_per_cu;  /* chosen resident workgroups per CU */
+    int order;         /* chosen work-queue order */
+    int trials;        /* trial launches timed */
+    float trial_ms;    /* the chosen trial's time */
+} lbm_batch_tuning_t;
+
+/* Time short persistent trials of the queued requests (each capped at
+ * trial_steps steps) for every workgroup size in {256, 384, 512, 768, 1024}
+ * that holds the tallest channel, times 1..4 resident workgroups per CU (LDS
+ * permitting, at most 2048 threads per CU), times both work-queue orders, and
+ * keep the fastest (results are identical for every choice). The queued
+ * requests stay queued. `out` may be NULL. */
+int lbm_batch_autotune(lbm_batch_t *b, int trial_steps, lbm_batch_tuning_t *out);
 
 int lbm_batch_stats(const lbm_batch_t *b, lbm_batch_stats_t *out);
 

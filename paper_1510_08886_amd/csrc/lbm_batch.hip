@@ -231,6 +231,7 @@ struct Req {
     int check_every;
     int64_t max_steps;
     double est;          // estimated work (for longest-first ordering)
+    uint64_t seq;        // submission order
     StepScalars<float> sc;
     double mdot_scale;
     double apart0[2][4];
@@ -262,7 +263,18 @@ struct Batch {
     PairTable<float> tabs[kBatchSets];
     int threads = 512;
     int quantum = 1000;
+    int slots_per_cu = 2;            // persistent mode: resident workgroups per CU (LDS permitting)
+    int order = LBM_BATCH_LONGEST_FIRST;   // persistent mode: work-queue order
+    uint64_t next_seq = 0;
     bool inflight = false;
+    // persistent launches captured once per launch shape and replayed
+    struct Graph {
+        int nact, grid, threads, rmax;
+        size_t lds;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    int64_t graph_replays = 0;
     hipEvent_t ev = nullptr;
     int64_t launches = 0;
     size_t max_lds = 65536;
@@ -442,36 +454,65 @@ static int serve_launch(Batch &b) {
     return LBM_OK;
 }
 
-// One persistent launch over all active slots, captured in a graph.
+// Resident workgroups of a persistent launch: slots_per_cu per CU as far as
+// the LDS of a CU allows, never more than the channels.
+static int persistent_grid(const Batch &b, size_t lds, int nact) {
+    const int per_cu = std::max<int>(1, (int)(b.max_lds / std::max<size_t>(lds, 1)));
+    return std::max(1, std::min<int>(nact, b.cus * std::min(per_cu, b.slots_per_cu)));
+}
+
+// One persistent launch over all active slots. The launch (work-counter reset
+// and the slot kernel, whose arguments are fixed pool addresses and the
+// channel count) is captured in a HIP graph once per launch shape and
+// replayed on later runs of the same shape; the slot table travels by copies
+// outside the graph.
 static int persistent_run(Batch &b) {
     if (b.active.empty()) return LBM_OK;
-    // longest estimated work first
-    std::stable_sort(b.active.begin(), b.active.end(),
-                     [](const Batch::Act &x, const Batch::Act &y) { return x.req.est > y.req.est; });
+    // the device work queue hands channels out in this order
+    if (b.order == LBM_BATCH_LONGEST_FIRST)   // LPT: balances the makespan
+        std::stable_sort(b.active.begin(), b.active.end(),
+                         [](const Batch::Act &x, const Batch::Act &y) { return x.req.est > y.req.est; });
+    else
+        std::stable_sort(b.active.begin(), b.active.end(),
+                         [](const Batch::Act &x, const Batch::Act &y) { return x.req.seq < y.req.seq; });
     int rc = upload(b);
     if (rc) return rc;
     int rmax = 1;
     const size_t lds = launch_lds(b, &rmax);
-    const int per_cu = std::max<int>(1, (int)(b.max_lds / std::max<size_t>(lds, 1)));
-    const int grid = std::min<int>((int)b.active.size(), b.cus * std::min(per_cu, 2));
-    hipGraph_t graph = nullptr;
+    const int nact = (int)b.active.size();
+    const int grid = persistent_grid(b, lds, nact);
     hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_ok(e, "graph capture begin");
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, b.stream, (int *)(b.pool + b.off_counter));
-    rc = launch_slots(b, (int)b.active.size(), true, INT64_MAX, lds, rmax, grid);
-    e = hipStreamEndCapture(b.stream, &graph);
-    if (rc) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
+    for (const auto &g : b.graphs)
+        if (g.nact == nact && g.grid == grid && g.threads == b.threads && g.rmax == rmax && g.lds == lds)
+            exec = g.exec;
+    hipError_t e = hipSuccess;
+    if (exec) {
+        ++b.graph_replays;
+    } else {
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_ok(e, "graph capture begin");
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, b.stream,
+                           (int *)(b.pool + b.off_counter));
+        rc = launch_slots(b, nact, true, INT64_MAX, lds, rmax, grid);
+        e = hipStreamEndCapture(b.stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_ok(e, "graph capture end");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_ok(e, "graph instantiate");
+        if (b.graphs.size() >= 8) {   // the stream is idle here: runs are blocking
+            (void)hipGraphExecDestroy(b.graphs.front().exec);
+            b.graphs.erase(b.graphs.begin());
+        }
+        b.graphs.push_back({nact, grid, b.threads, rmax, lds, exec});
     }
-    if (e != hipSuccess) return hip_ok(e, "graph capture end");
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, b.stream);
+    e = hipGraphLaunch(exec, b.stream);
     if (e == hipSuccess) rc = download(b);
     if (e == hipSuccess && !rc) e = hipStreamSynchronize(b.stream);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_ok(e, "graph launch");
     if (rc) return rc;
     return harvest(b);
@@ -531,6 +572,7 @@ extern "C" int lbm_batch_destroy(lbm_batch_t *h) {
     Batch *b = reinterpret_cast<Batch *>(h);
     if (b->inflight) (void)hipEventSynchronize(b->ev);
     (void)hipStreamSynchronize(b->stream);
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     if (b->ev) (void)hipEventDestroy(b->ev);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->h_active) (void)hipHostFree(b->h_active);
@@ -587,6 +629,7 @@ extern "C" int lbm_batch_submit(lbm_batch_t *h, const lbm_dvm_t *dvm, const lbm_
     r.mdot_scale = par.mdot_scale;
     // work ~ nodes x steps to converge, steps ~ c ny / tau (a diffusion time)
     r.est = (double)prob->ny * prob->ny * d.c / par.tau;
+    r.seq = b.next_seq++;
     // rest-state wall partials: w rho0 of the populations leaving from each wall row
     for (int f = 0; f < 2; ++f)
         for (int rr = 0; rr < 4; ++rr) {
@@ -673,8 +716,10 @@ extern "C" int lbm_batch_run_persistent(lbm_batch_t *h, lbm_result_t *out, int c
     return LBM_OK;
 }
 
-extern "C" int lbm_batch_tune(lbm_batch_t *h, int threads, int quantum) {
-    if (!h || threads < 64 || threads > 1024 || threads % 64 || quantum < 1)
+extern "C" int lbm_batch_tune(lbm_batch_t *h, int threads, int quantum, int slots_per_cu,
+                              int order) {
+    if (!h || threads < 64 || threads > 1024 || threads % 64 || quantum < 1 || slots_per_cu < 0 ||
+        slots_per_cu > 16 || order < 0 || order > LBM_BATCH_SUBMIT_ORDER)
         return fail(LBM_E_INVALID, "lbm_batch_tune: bad arguments");
     Batch &b = *reinterpret_cast<Batch *>(h);
     int maxny = 0;
@@ -685,53 +730,80 @@ extern "C" int lbm_batch_tune(lbm_batch_t *h, int threads, int quantum) {
                                    "twice that many rows");
     b.threads = threads;
     b.quantum = quantum;
+    if (slots_per_cu > 0) b.slots_per_cu = slots_per_cu;
+    if (order > 0) b.order = order;
     return LBM_OK;
 }
 
-extern "C" int lbm_batch_autotune(lbm_batch_t *h, int trial_steps, int *threads_out) {
+// Autotuner of the persistent launch: every workgroup size that can hold the
+// tallest channel (which fixes the rows per thread: one, or two where the
+// channel is taller than the workgroup) times 1 to 4 resident workgroups per
+// CU times both work-queue orders, each timed on a trial of the queued
+// requests capped at trial_steps steps. Results do not depend on the choice.
+extern "C" int lbm_batch_autotune(lbm_batch_t *h, int trial_steps, lbm_batch_tuning_t *out) {
     if (!h || trial_steps < 1) return fail(LBM_E_INVALID, "lbm_batch_autotune: bad arguments");
     Batch &b = *reinterpret_cast<Batch *>(h);
     if (b.inflight || !b.active.empty())
         return fail(LBM_E_INVALID, "lbm_batch_autotune: batch must be idle");
+    lbm_batch_tuning_t res{b.threads, b.slots_per_cu, b.order, 0, 0.0f};
     if (b.queue.empty()) {
-        if (threads_out) *threads_out = b.threads;
+        if (out) *out = res;
         return LBM_OK;
     }
     const std::deque<Req> saved = b.queue;
     int maxny = 0;
-    for (auto &r : saved) maxny = std::max(maxny, r.ny);
+    size_t maxlds = 0;
+    for (auto &r : saved) {
+        maxny = std::max(maxny, r.ny);
+        maxlds = std::max(maxlds, b.lds_bytes(r));
+    }
+    const int lds_per_cu = std::max<int>(1, (int)(b.max_lds / std::max<size_t>(maxlds, 1)));
     const int cands[] = {256, 384, 512, 768, 1024};
     float best = 1e30f;
-    int best_t = b.threads;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(LBM_E_DEVICE, "lbm_batch_autotune: events");
     int rc = LBM_OK;
     for (int th : cands) {
         if (2 * th < maxny) continue;
-        b.threads = th;
-        b.queue = saved;
-        for (auto &r : b.queue) r.max_steps = std::min<int64_t>(r.max_steps, trial_steps);
-        rc = admit(b, true);
-        if (rc) break;
-        (void)hipEventRecord(e0, b.stream);
-        rc = persistent_run(b);   // harvests every trial channel
-        (void)hipEventRecord(e1, b.stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        b.done.clear();
-        if (rc) break;
-        if (ms < best) {
-            best = ms;
-            best_t = th;
+        for (int sp = 1; sp <= std::min(4, lds_per_cu) && rc == LBM_OK; ++sp) {
+            // more resident workgroups than 2048 threads per CU gain nothing
+            if (sp > 1 && sp * th > 2048) continue;
+            for (int order = LBM_BATCH_LONGEST_FIRST; order <= LBM_BATCH_SUBMIT_ORDER; ++order) {
+                b.threads = th;
+                b.slots_per_cu = sp;
+                b.order = order;
+                b.queue = saved;
+                for (auto &r : b.queue) r.max_steps = std::min<int64_t>(r.max_steps, trial_steps);
+                rc = admit(b, true);
+                if (rc) break;
+                (void)hipEventRecord(e0, b.stream);
+                rc = persistent_run(b);   // harvests every trial channel
+                (void)hipEventRecord(e1, b.stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                b.done.clear();
+                if (rc) break;
+                ++res.trials;
+                if (ms < best) {
+                    best = ms;
+                    res.threads = th;
+                    res.slots_per_cu = sp;
+                    res.order = order;
+                    res.trial_ms = ms;
+                }
+            }
         }
+        if (rc) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b.queue = saved;
-    b.threads = best_t;
-    if (threads_out) *threads_out = best_t;
+    b.threads = res.threads;
+    b.slots_per_cu = res.slots_per_cu;
+    b.order = res.order;
+    if (out) *out = res;
     return rc;
 }
 
@@ -743,6 +815,9 @@ extern "C" int lbm_batch_stats(const lbm_batch_t *h, lbm_batch_stats_t *out) {
     out->done = (int)b.done.size();
     out->threads = b.threads;
     out->quantum = b.quantum;
+    out->slots_per_cu = b.slots_per_cu;
+    out->order = b.order;
+    out->graph_replays = b.graph_replays;
     out->launches = b.launches;
     out->pool_used = b.used;
     out->pool_free = b.heap_free();

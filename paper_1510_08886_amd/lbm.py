@@ -81,9 +81,18 @@ class ProfileStatsC(ctypes.Structure):
                 ("slip", ctypes.c_double), ("mean", ctypes.c_double)]
 
 
+class BatchTuningC(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int), ("slots_per_cu", ctypes.c_int), ("order", ctypes.c_int),
+                ("trials", ctypes.c_int), ("trial_ms", ctypes.c_float)]
+
+
+BATCH_ORDERS = {1: "longest_first", 2: "submit"}
+
+
 class BatchStatsC(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int), ("queued", ctypes.c_int), ("done", ctypes.c_int),
-                ("threads", ctypes.c_int), ("quantum", ctypes.c_int), ("launches", ctypes.c_int64),
+                ("threads", ctypes.c_int), ("quantum", ctypes.c_int), ("slots_per_cu", ctypes.c_int),
+                ("order", ctypes.c_int), ("graph_replays", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("pool_used", ctypes.c_size_t), ("pool_free", ctypes.c_size_t)]
 
 
@@ -128,8 +137,8 @@ SIGNATURES = {
     "lbm_batch_poll": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
     "lbm_batch_drain": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
     "lbm_batch_run_persistent": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
-    "lbm_batch_tune": ([_P, _I, _I], _I),
-    "lbm_batch_autotune": ([_P, _I, _IP], _I),
+    "lbm_batch_tune": ([_P, _I, _I, _I, _I], _I),
+    "lbm_batch_autotune": ([_P, _I, _P], _I),
     "lbm_batch_stats": ([_P, ctypes.POINTER(BatchStatsC)], _I),
     "lbm_stream_copy": ([_P, _P, ctypes.c_size_t, _P], _I),
     "lbm_dvm_enumerate": ([_I, _I, _I, _I, _I, _P, _I, _IP], _I),
@@ -537,14 +546,20 @@ class Batch:
     def run_persistent(self):
         return self._call(lib().lbm_batch_run_persistent, "lbm_batch_run_persistent")
 
-    def tune(self, threads: int, quantum: int = 1000):
-        check(lib().lbm_batch_tune(self._h, int(threads), int(quantum)), "lbm_batch_tune")
+    def tune(self, threads: int, quantum: int = 1000, slots_per_cu: int = 0, order=None):
+        order = {None: 0, 0: 0, "longest_first": 1, "submit": 2}[order]
+        check(lib().lbm_batch_tune(self._h, int(threads), int(quantum), int(slots_per_cu), order),
+              "lbm_batch_tune")
         return self
 
-    def autotune(self, trial_steps: int = 300) -> int:
-        t = ctypes.c_int()
-        check(lib().lbm_batch_autotune(self._h, int(trial_steps), ctypes.byref(t)), "lbm_batch_autotune")
-        return t.value
+    def autotune(self, trial_steps: int = 300) -> dict:
+        """Workgroup size, resident workgroups per CU and work-queue order of
+        the persistent launch, chosen by timing trials (lbm_batch_autotune)."""
+        t = BatchTuningC()
+        check(lib().lbm_batch_autotune(self._h, int(trial_steps), ctypes.byref(t)),
+              "lbm_batch_autotune")
+        return dict(threads=t.threads, slots_per_cu=t.slots_per_cu,
+                    order=BATCH_ORDERS[t.order], trials=t.trials, trial_ms=round(t.trial_ms, 4))
 
     def stats(self):
         st = BatchStatsC()

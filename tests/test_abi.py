@@ -189,3 +189,35 @@ def test_problems_beyond_32_bit_indices_are_refused():
     pop, _ = lbm.state_bytes(d, lbm.Problem(dim=3, nx=128, ny=512, nz=1024, kn=0.1,
                                             hermite_order=3, storage="f16dev"))
     assert pop == 2 * 39 * 128 * 512 * 1024 * 2
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every public struct of the header has the size and field offsets that
+    the Python binding's ctypes mirror assumes (checked with gcc against the
+    header itself)."""
+    import ctypes
+    import subprocess
+
+    from paper_1510_08886_amd import lbm
+    pairs = {"lbm_problem_t": lbm.ProblemC, "lbm_params_t": lbm.ParamsC,
+             "lbm_result_t": lbm.ResultC, "lbm_wall_report_t": lbm.WallReportC,
+             "lbm_dvm_model_t": lbm.DvmModelC, "lbm_profile_stats_t": lbm.ProfileStatsC,
+             "lbm_batch_tuning_t": lbm.BatchTuningC, "lbm_batch_stats_t": lbm.BatchStatsC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbmdvm.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", str(ROOT / "include"), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -8,7 +8,11 @@ to a steady-state tolerance on the mass flow).
 * a channel's result is the same alone and in a mix, for any workgroup size,
   in the persistent (graph) mode and in the served mode, bit for bit;
 * admission by memory: a pool too small for all requests defers some and still
-  finishes every one with the same results.
+  finishes every one with the same results;
+* every channel of the 64-channel Kn sweep and a stored sample of the serving
+  trace against the FP64 oracle's mass flow at the same step (Eq. pf.1);
+* the autotuner's choices (workgroup size, resident workgroups per CU, queue
+  order) keep results bit for bit, and persistent graphs are replayed.
 """
 import numpy as np
 import pytest
@@ -126,9 +130,130 @@ def test_step_cap_reports_not_converged(dvms):
 
 def test_autotune_keeps_results(dvms):
     b = _batch(dvms, CHANNELS)
-    threads = b.autotune(200)
-    assert threads in (256, 384, 512, 768, 1024)
+    t = b.autotune(200)
+    assert t["threads"] in (256, 384, 512, 768, 1024)
+    assert 1 <= t["slots_per_cu"] <= 4 and t["order"] in ("longest_first", "submit")
+    assert t["trials"] >= 2
     got = _by_id(b.run_persistent())
+    # the timed run has the winning trial's launch shape: its graph is replayed
+    assert b.stats()["graph_replays"] >= 1
     ref = _by_id(_batch(dvms, CHANNELS).run_persistent())
     for k in ref:
         assert got[k]["mdot"] == ref[k]["mdot"] and got[k]["steps"] == ref[k]["steps"]
+
+
+@pytest.mark.parametrize("slots_per_cu,order", [(1, "submit"), (3, "longest_first"), (4, "submit")])
+def test_grid_and_queue_order_keep_results(dvms, slots_per_cu, order):
+    """Resident workgroups per CU and the work-queue order change which
+    workgroup steps a channel, never its result (bit for bit)."""
+    ref = _by_id(_batch(dvms, CHANNELS).run_persistent())
+    b = _batch(dvms, CHANNELS)
+    b.tune(384, slots_per_cu=slots_per_cu, order=order)
+    got = _by_id(b.run_persistent())
+    st = b.stats()
+    assert st["slots_per_cu"] == slots_per_cu and st["threads"] == 384
+    for k in ref:
+        assert got[k]["mdot"] == ref[k]["mdot"] and got[k]["steps"] == ref[k]["steps"]
+
+
+def test_persistent_graph_is_replayed(dvms):
+    """A second persistent run of the same launch shape replays the captured
+    graph and gives the same results."""
+    from paper_1510_08886_amd import lbm
+    b = _batch(dvms, CHANNELS)
+    first = _by_id(b.run_persistent())
+    assert b.stats()["graph_replays"] == 0
+    for k, (name, ny, kn) in enumerate(CHANNELS):
+        b.submit(dvms[name], ny, kn, N=lbm.NAMED_DVMS[name]["N"], tol=1e-8, max_steps=400000,
+                 req_id=k)
+    second = _by_id(b.run_persistent())
+    assert b.stats()["graph_replays"] == 1
+    for k in first:
+        assert first[k]["mdot"] == second[k]["mdot"] and first[k]["steps"] == second[k]["steps"]
+
+
+def test_tune_rejects_bad_arguments(dvms):
+    from paper_1510_08886_amd import lbm
+    b = _batch(dvms, CHANNELS)
+    for kw in (dict(threads=100), dict(threads=256, slots_per_cu=17), dict(threads=256, quantum=0)):
+        with pytest.raises(lbm.LbmError):
+            b.tune(**kw)
+    b.close()
+    b = _batch(dvms, [("D2V37", 300, 0.5)])
+    with pytest.raises(lbm.LbmError):   # 300 rows need more than 128 threads x 2 rows
+        b.tune(128)
+    b.tune(192)
+    b.close()
+
+
+def _sweep_errors(storage, caps=None, tol=1e-8):
+    import lbm_workloads as wl
+    from paper_1510_08886_amd import serve
+    from tests.golden.converged import SWEEP, load_converged, rel_err_at
+    cfg = wl.SWEEP
+    chans = wl.sweep_channels(cfg["channels"], seed=cfg["seed"])
+    if not SWEEP.exists():
+        pytest.skip("oracle golden of the sweep not generated (make_converged_golden)")
+    gold = load_converged(SWEEP)
+    assert sorted(gold) == list(range(cfg["channels"]))
+    for k, g in gold.items():
+        assert (chans[k]["ny"], chans[k]["kn"]) == (g["ny"], g["kn"])
+    r = serve.batched_sweep(chans, storage=storage, tol=tol, check_every=cfg["check_every"],
+                            max_steps=caps if caps is not None else 2_000_000, autotune=False)
+    return r["results"], gold, [rel_err_at(gold[k], x["steps"], x["mdot"])
+                                for k, x in enumerate(r["results"])]
+
+
+def test_full_sweep_matches_oracle_at_every_stop_step():
+    """All 64 channels of the Kn sweep (FP32, tol 1e-8): each converges, within
+    two checks of the oracle's own stop step, with a mass flow within 1e-5 of
+    the oracle's at the same step; FP16 deviations stepped to the same counts
+    stay within 1e-3."""
+    res, gold, err = _sweep_errors("f32")
+    for k, (x, e) in enumerate(zip(res, err)):
+        assert x["status"] == "converged", (k, x)
+        assert abs(x["steps"] - gold[k]["stop"]) <= 200, (k, x["steps"], gold[k]["stop"])
+        assert e is not None and e <= 1e-5, (k, x, e)
+    steps = [x["steps"] for x in res]
+    res16, _, err16 = _sweep_errors("f16dev", caps=steps, tol=1e-300)
+    for k, (x, e) in enumerate(zip(res16, err16)):
+        assert x["steps"] == steps[k]
+        assert e is not None and e <= 1e-3, (k, x, e)
+
+
+def test_served_sample_matches_oracle():
+    """The stored oracle sample of the serving trace (both DVMs, Ny quarters):
+    each request served through the polled engine converges at a step whose
+    oracle mass flow is within 1e-5 of the served one."""
+    import time
+
+    import lbm_workloads as wl
+    from paper_1510_08886_amd import lbm
+    from tests.golden.converged import SERVE, load_converged, rel_err_at
+    if not SERVE.exists():
+        pytest.skip("oracle golden of the serving sample not generated (make_converged_golden)")
+    gold = load_converged(SERVE)
+    assert len(gold) >= 30
+    cfg = wl.SERVE
+    trace = wl.serve_trace(cfg["requests"], seed=cfg["seed"], rate=cfg["rate"])
+    names = {g["dvm"] for g in gold.values()}
+    assert names == {"D2V17", "D2V37"}
+    dv = {n: lbm.Dvm.named(n) for n in names}
+    b = lbm.Batch(64, storage="f32", pool_bytes=256 << 20)
+    b.tune(512, 1000)
+    for k, g in gold.items():
+        assert (trace[k]["ny"], trace[k]["kn"], trace[k]["dvm"]) == (g["ny"], g["kn"], g["dvm"])
+        b.submit(dv[g["dvm"]], g["ny"], g["kn"], N=lbm.NAMED_DVMS[g["dvm"]]["N"], tol=cfg["tol"],
+                 check_every=cfg["check_every"], max_steps=2_000_000, req_id=k)
+    res = []
+    t_end = time.time() + 90
+    while len(res) < len(gold) and time.time() < t_end:
+        res += b.poll()
+    b.close()
+    got = _by_id(res)
+    assert sorted(got) == sorted(gold)
+    for k, g in gold.items():
+        x = got[k]
+        assert x["status"] == "converged", (k, x)
+        e = rel_err_at(g, x["steps"], x["mdot"])
+        assert e is not None and e <= 1e-5, (k, x, g["stop"], e)
