@@ -439,6 +439,18 @@ int lbm_batch_stats(const lbm_batch_t *b, lbm_batch_stats_t *out);
  * LBM_E_INVALID on a bad argument, LBM_E_DEVICE if the launch fails. */
 int lbm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/* Duration of individual step launches: n times lbm_run(s, steps_per_launch),
+ * each bracketed by HIP events recorded on `stream`, which must be the
+ * solver's stream (the one it was created with), blocking until all have run; ms_out[k] (host, n floats) receives the
+ * k-th run's event-to-event time. system_scope = 1 records the events with a
+ * system-scope release (the GPU's caches are written back at each event, as
+ * a per-dispatch kernel trace does), 0 with the default device scope.
+ * steps_per_launch must match the solver's launch (1 for single steps, 2 for
+ * two steps per launch). LBM_E_INVALID on a bad argument, LBM_E_DEVICE on a
+ * runtime error. */
+int lbm_time_launches(lbm_solver_t *s, void *stream, int n, int steps_per_launch,
+                      int system_scope, float *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

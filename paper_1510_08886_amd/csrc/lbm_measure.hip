@@ -3,6 +3,9 @@
 // (next to the 8 TB/s peak of the part).
 #include <hip/hip_runtime.h>
 
+#include <string>
+#include <vector>
+
 #include "lbm_internal.h"
 
 using namespace lbm;
@@ -35,5 +38,33 @@ extern "C" int lbm_stream_copy(const void *src, void *dst, size_t bytes, void *s
                        (const u32x4 *)src, (u32x4 *)dst, n);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("lbm_stream_copy: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// Event-to-event duration of individual lbm_run calls on the solver's stream.
+extern "C" int lbm_time_launches(lbm_solver_t *h, void *stream, int n, int steps_per_launch,
+                                 int system_scope, float *ms_out) {
+    if (!h || n < 1 || n > 100000 || steps_per_launch < 1 || !ms_out)
+        return fail(LBM_E_INVALID, "lbm_time_launches: bad arguments");
+    const hipStream_t st = (hipStream_t)stream;
+    const unsigned flags = system_scope ? hipEventReleaseToSystem : hipEventDefault;
+    std::vector<hipEvent_t> ev(n + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x, flags);
+    int rc = LBM_OK;
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    for (int k = 0; k < n && e == hipSuccess && rc == LBM_OK; ++k) {
+        rc = lbm_run(h, steps_per_launch);
+        if (rc == LBM_OK) e = hipEventRecord(ev[k + 1], st);
+    }
+    if (e == hipSuccess && rc == LBM_OK) e = hipEventSynchronize(ev[n]);
+    for (int k = 0; k < n && e == hipSuccess && rc == LBM_OK; ++k)
+        e = hipEventElapsedTime(&ms_out[k], ev[k], ev[k + 1]);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc) return rc;
+    if (e != hipSuccess)
+        return fail(LBM_E_DEVICE, std::string("lbm_time_launches: ") + hipGetErrorString(e));
     return LBM_OK;
 }

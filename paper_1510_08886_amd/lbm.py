@@ -137,6 +137,7 @@ SIGNATURES = {
     "lbm_batch_poll": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
     "lbm_batch_drain": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
     "lbm_batch_run_persistent": ([_P, ctypes.POINTER(ResultC), _I, _IP], _I),
+    "lbm_time_launches": ([_P, _P, _I, _I, _I, _P], _I),
     "lbm_batch_tune": ([_P, _I, _I, _I, _I], _I),
     "lbm_batch_autotune": ([_P, _I, _P], _I),
     "lbm_batch_stats": ([_P, ctypes.POINTER(BatchStatsC)], _I),
@@ -442,6 +443,16 @@ class Solver:
               "lbm_observe")
         return dict(rho=rho.reshape(self.shape), u=u.reshape(self.shape + (3,)),
                     mdot=md.value, mass=mass.value)
+
+    def time_launches(self, n: int, steps_per_launch: int = 1, system_scope: bool = False):
+        """Event-to-event durations (ms) of n runs of steps_per_launch steps
+        each (lbm_time_launches; a measurement aid)."""
+        import numpy as np
+        out = np.zeros(int(n), dtype=np.float32)
+        check(lib().lbm_time_launches(self._h, _P(self.stream.cuda_stream), int(n),
+                                      int(steps_per_launch), int(bool(system_scope)),
+                                      out.ctypes.data_as(_P)), "lbm_time_launches")
+        return out
 
     def mdot(self) -> float:
         md = ctypes.c_double()

@@ -93,6 +93,28 @@ def test_graph_replay_ping_pong_path():
     b.close()
 
 
+def test_graph_cache_eviction_and_teardown_in_flight():
+    """More distinct step sequences than the solver caches graphs for (8): the
+    oldest graphs are destroyed while later replays are queued, and solvers are
+    destroyed with replays still in flight; every result stays equal to one
+    launch per step, and a solver created after the teardown steps correctly."""
+    a, b = _pair("D2V17", 3, 1, 300, storage="f64", graph=64)
+    for n in (2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 2, 4, 22, 64, 130):
+        a.run(n)
+        b.run(n)
+    assert torch.equal(a.export(), b.export())
+    # teardown with replays queued behind a long sequence
+    a.run(640)
+    a.close()
+    b.close()
+    c, d = _pair("D2V17", 3, 1, 300, storage="f64", graph=64)
+    c.run(300)
+    d.run(300)
+    assert torch.equal(c.export(), d.export())
+    c.close()
+    d.close()
+
+
 @pytest.mark.parametrize("name,N,nx,ny,storage", [
     ("D2V17", 3, 1, 40, "f64"),      # the launch-bound FP64 channel
     ("D2V37", 4, 20, 12, "f32"),     # 240 nodes, wall rows on both sides

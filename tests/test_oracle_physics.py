@@ -366,3 +366,38 @@ def test_channel_golden_file_matches_oracle():
     ob = o.observe()
     assert abs(ob["mdot"] - kv["mdot"]) <= 1e-14 * kv["mdot"]
     assert np.max(np.abs(ob["u"][:, 0, 0] - ux)) <= 1e-14 * np.max(ux)
+
+
+def test_converged_golden_files_match_recipes_and_oracle():
+    """The stored converged oracle runs (tests/golden/sweep_d2v37_converged.txt,
+    serve_sample_converged.txt) belong to the current sweep recipe and serving
+    sample; each solve stopped at the first check whose relative change was
+    below the tolerance; and re-running the oracle on the cheapest stored solve
+    reproduces its first stored value."""
+    from tests.golden import make_converged_golden as mcg
+    from tests.golden.converged import SERVE, SWEEP, load_converged
+    for path, jobs in ((SWEEP, mcg.sweep_jobs()), (SERVE, mcg.serve_sample())):
+        if not path.exists():
+            pytest.skip(f"{path.name} not generated yet")
+        gold = load_converged(path)
+        assert sorted(gold) == sorted(j[0] for j in jobs)
+        for key, name, ny, kn in jobs:
+            g = gold[key]
+            assert (g["dvm"], g["ny"], g["kn"]) == (name, ny, kn)
+            assert g["stop"] is not None
+            steps = sorted(g["mdot"])
+            assert steps[-1] == g["stop"] + mcg.WINDOW_AFTER
+            assert all(b - a == mcg.CHECK for a, b in zip(steps, steps[1:]))
+            m = g["mdot"]
+            # the stop is the first stored check meeting the tolerance
+            for s in steps[1:]:
+                rel = abs(m[s] - m[s - mcg.CHECK]) < mcg.TOL * abs(m[s])
+                assert rel == (s >= g["stop"]) or s > g["stop"], (key, s)
+            assert abs(m[g["stop"]] - m[g["stop"] - mcg.CHECK]) < mcg.TOL * abs(m[g["stop"]])
+        key = min(gold, key=lambda k: gold[k]["ny"] * min(gold[k]["mdot"]))
+        g = gold[key]
+        s0 = min(g["mdot"])
+        o = stepper.OracleSolver(dvm.named_dvm(g["dvm"]), nx=1, ny=g["ny"], kn=g["kn"], ma=1e-3,
+                                 N=mcg.N_OF[g["dvm"]]).init()
+        o.run(s0)
+        assert abs(o.observe()["mdot"] - g["mdot"][s0]) <= 1e-14 * abs(g["mdot"][s0])
