@@ -45,17 +45,24 @@ typedef struct lbm_dvm lbm_dvm_t;
 typedef struct lbm_solver lbm_solver_t;
 typedef struct lbm_batch lbm_batch_t;
 
-/* Population storage. The collision is FP64 for LBM_F64 and FP32 otherwise;
- * the wall-flux balance and the mass-flux reductions are FP64 in every mode.
- * Every post-collision population is rounded to the storage type every step. */
+/* Population storage. The collision is FP64 for LBM_F64 and LBM_F32SR and
+ * FP32 otherwise; the wall-flux balance and the mass-flux reductions are FP64
+ * in every mode. Every post-collision population is rounded to the storage
+ * type every step. */
 enum lbm_storage {
     LBM_F64 = 0,     /* fbar in double */
     LBM_F32 = 1,     /* fbar as the FP32 deviation fbar - w rho0 (round to nearest) */
     LBM_F16DEV = 2,  /* half-precision scaled deviation fbar / (w rho0) - 1, rounded
                         stochastically with a counter-based hash of (node, velocity,
                         step): unbiased, deterministic and reproducible */
-    LBM_F32RAW = 3   /* fbar itself in FP32 (round to nearest); its rounding step is
+    LBM_F32RAW = 3,  /* fbar itself in FP32 (round to nearest); its rounding step is
                         ~6e-8 of w rho0, so slow relaxations stagnate early */
+    LBM_F32SR = 4    /* the FP32 deviation of LBM_F32, collided in FP64 and rounded
+                        stochastically (key as for LBM_F16DEV): the same bytes, no
+                        bias that accumulates over a long relaxation (round to
+                        nearest repeats the same error at a steady state every
+                        step). 2D channels of D2V17 and D2V37 (LBM_E_UNSUPPORTED
+                        otherwise) */
 };
 
 /* Population layout in HBM. Both give identical results; the choice only

@@ -33,6 +33,7 @@ size_t storage_bytes(int s) {
         case LBM_F32: return 4;
         case LBM_F16DEV: return 2;
         case LBM_F32RAW: return 4;
+        case LBM_F32SR: return 4;
         default: return 0;
     }
 }
@@ -295,7 +296,7 @@ static void fill_tables(const Dvm &d, const lbm_problem_t &p, const lbm_params_t
     s->alpha = p.accommodation;
     s->specular = p.accommodation < 1.0 ? 1 : 0;
     // w rho0 of the populations that leave through each face from wall row r
-    const bool dev_storage = p.storage == LBM_F32 || p.storage == LBM_F16DEV;
+    const bool dev_storage = deviation_storage((Storage)p.storage);
     for (int r = 0; r < kMaxWallRows; ++r) {
         double k[4] = {0, 0, 0, 0};
         for (int v = 0; v < d.V; ++v) {
@@ -450,18 +451,17 @@ int lbm::solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *po
     s->stream = (hipStream_t)stream;
     s->nodes = nodes_of(*prob);
     s->graph_steps =
-        (graphs && st != Storage::F16DEV && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
+        (graphs && !stochastic_storage(st) && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
     s->graphs_allowed = graphs;
     s->resident_steps = resident_ok(*s) ? kResidentMaxSteps : 0;
-    // two steps per launch where compiled, for ping-pong problems not already
-    // stepped from graphs
     // two steps per launch for ping-pong problems not stepped from graphs,
     // producer and consumer waves (mode 2). Measured on MI355X, D2V37 FP32
     // 4096 x 2048 (1.24 GB per copy): 303 us per step against 437 us for one
     // launch per step. FP16 deviations keep single steps: their step is
-    // bound by its arithmetic (252 against 319 us).
-    s->pair_steps = (pair_ok(*s) && s->graph_steps == 0 && st != Storage::F16DEV) ? 2 : 0;
-    if (st == Storage::F64)
+    // bound by its arithmetic (252 against 319 us); so do FP32SR's (FP64
+    // collision).
+    s->pair_steps = (pair_ok(*s) && s->graph_steps == 0 && !stochastic_storage(st)) ? 2 : 0;
+    if (st == Storage::F64 || st == Storage::F32SR)
         fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
     else
         fill_tables<float>(d, *prob, s->par, s->tab, s->sc);
@@ -647,8 +647,8 @@ extern "C" int lbm_solver_set_pair_steps(lbm_solver_t *h, int on, int band_rows)
 extern "C" int lbm_solver_set_graph_steps(lbm_solver_t *h, int max_steps) {
     if (!h || max_steps < 0) return fail(LBM_E_INVALID, "lbm_solver_set_graph_steps: bad arguments");
     Solver &s = *reinterpret_cast<Solver *>(h);
-    if (max_steps > 0 && s.st == Storage::F16DEV)
-        return fail(LBM_E_UNSUPPORTED, "graph replay: FP16 stochastic rounding keys on the step");
+    if (max_steps > 0 && stochastic_storage(s.st))
+        return fail(LBM_E_UNSUPPORTED, "graph replay: stochastic rounding keys on the step");
     if (max_steps > 0 && !s.graphs_allowed)
         return fail(LBM_E_UNSUPPORTED, "graph replay: this solver allocates nothing (static scratch)");
     s.graph_steps = std::min(max_steps, 4096);

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <type_traits>
 #include <vector>
 
 #include "lbm_node2d.h"
@@ -47,8 +48,17 @@ struct SlotDesc {
     double mdot_scale;
     uint64_t pop_off;    // byte offset of the stored populations in the pool
     double apart[2][4];  // FP64 wall-flux partials [face][row]
-    StepScalars<float> sc;
+    StepScalars<float> sc;     // FP32 collision
+    StepScalars<double> scd;   // FP64 collision (LBM_F32SR)
 };
+
+template <typename R>
+__device__ __forceinline__ const StepScalars<R> &slot_scalars(const SlotDesc *d) {
+    if constexpr (std::is_same<R, double>::value)
+        return d->scd;
+    else
+        return d->sc;
+}
 
 // LDS bytes one slot needs: populations, the padded reduction tree, partials
 __host__ __device__ inline size_t slot_lds_bytes(int V, int ny, int elem) {
@@ -59,14 +69,15 @@ __host__ __device__ inline size_t slot_lds_bytes(int V, int ny, int elem) {
 }
 
 template <class SET, Storage S, int RMAX>
-__device__ void run_slot(unsigned char *pool, SlotDesc *d, const PairTable<float> &t,
-                         unsigned char *lds, int64_t quantum) {
+__device__ __forceinline__ void run_slot(unsigned char *pool, SlotDesc *d,
+                                         const PairTable<typename St<S>::R> &t, unsigned char *lds,
+                                         int64_t quantum) {
     using T = typename St<S>::T;
     using R = typename St<S>::R;
     constexpr int V = SET::V, NR = SET::NR, HN = SET::HN;
     const int ny = d->ny;
     const int TH = blockDim.x;
-    const StepScalars<R> &s = d->sc;
+    const StepScalars<R> &s = slot_scalars<R>(d);
     T *f = (T *)lds;
     int P = 1;
     while (P < ny) P <<= 1;
@@ -186,10 +197,15 @@ __device__ void run_slot(unsigned char *pool, SlotDesc *d, const PairTable<float
 // counter == nullptr: workgroup b runs slot active[b] for `quantum` steps.
 // Otherwise workgroups take slots from the device work queue until it is
 // exhausted; every workgroup leaves once the counter passes nactive.
-template <Storage S, int RMAX>
-__global__ __launch_bounds__(1024) void k_slots(unsigned char *pool, SlotDesc *descs,
-                                                const PairTable<float> *tabs, const int *active,
+// MAXT is the largest workgroup the instance is launched with: the register
+// budget per thread follows from it (1024 threads leave 128 VGPRs, which the
+// node state of two rows per thread overflows into scratch memory).
+template <Storage S, int RMAX, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_slots(unsigned char *pool, SlotDesc *descs,
+                                                const void *tab_mem, const int *active,
                                                 int nactive, int *counter, int64_t quantum) {
+    using R = typename St<S>::R;
+    const auto *tabs = (const PairTable<R> *)tab_mem;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int s_idx;
     int k = blockIdx.x;
@@ -233,6 +249,7 @@ struct Req {
     double est;          // estimated work (for longest-first ordering)
     uint64_t seq;        // submission order
     StepScalars<float> sc;
+    StepScalars<double> scd;
     double mdot_scale;
     double apart0[2][4];
 };
@@ -323,21 +340,31 @@ struct Batch {
 static int launch_slots(Batch &b, int nact, bool persistent, int64_t quantum, size_t lds,
                         int rmax, int grid) {
     auto *descs = (SlotDesc *)(b.pool + b.off_desc);
-    auto *tabs = (const PairTable<float> *)(b.pool + b.off_tabs);
+    const void *tabs = b.pool + b.off_tabs;
     auto *act = (const int *)(b.pool + b.off_active);
     int *counter = persistent ? (int *)(b.pool + b.off_counter) : nullptr;
     const dim3 blk(b.threads), grd(grid);
+#define LBM_SLOTS_T(SS, RM, MT)                                                                  \
+    hipLaunchKernelGGL((k_slots<SS, RM, MT>), grd, blk, lds, b.stream, b.pool, descs, tabs, act,  \
+                       nact, counter, quantum)
 #define LBM_SLOTS(SS, RM)                                                                        \
-    hipLaunchKernelGGL((k_slots<SS, RM>), grd, blk, lds, b.stream, b.pool, descs, tabs, act, nact, \
-                       counter, quantum)
+    do {                                                                                         \
+        if (b.threads <= 256) LBM_SLOTS_T(SS, RM, 256);                                          \
+        else if (b.threads <= 512) LBM_SLOTS_T(SS, RM, 512);                                     \
+        else if (b.threads <= 768) LBM_SLOTS_T(SS, RM, 768);                                     \
+        else LBM_SLOTS_T(SS, RM, 1024);                                                          \
+    } while (0)
     if (b.st == Storage::F32) {
         if (rmax == 1) LBM_SLOTS(Storage::F32, 1); else LBM_SLOTS(Storage::F32, 2);
     } else if (b.st == Storage::F16DEV) {
         if (rmax == 1) LBM_SLOTS(Storage::F16DEV, 1); else LBM_SLOTS(Storage::F16DEV, 2);
+    } else if (b.st == Storage::F32SR) {
+        if (rmax == 1) LBM_SLOTS(Storage::F32SR, 1); else LBM_SLOTS(Storage::F32SR, 2);
     } else {
         if (rmax == 1) LBM_SLOTS(Storage::F32RAW, 1); else LBM_SLOTS(Storage::F32RAW, 2);
     }
 #undef LBM_SLOTS
+#undef LBM_SLOTS_T
     ++b.launches;
     return hip_ok(hipGetLastError(), "batched kernel launch");
 }
@@ -368,6 +395,7 @@ static int admit(Batch &b, bool all_or_error) {
         d.pop_off = off;
         std::memcpy(d.apart, r.apart0, sizeof(d.apart));
         d.sc = r.sc;
+        d.scd = r.scd;
         b.active.push_back({slot, r, off, b.state_bytes(r)});
     }
     b.queue = keep;
@@ -527,8 +555,9 @@ extern "C" int lbm_batch_create(int max_slots, int storage, void *pool, size_t p
     if (!out || max_slots < 1 || !pool || (uintptr_t)pool % 256)
         return fail(LBM_E_INVALID, "lbm_batch_create: bad arguments");
     *out = nullptr;
-    if (storage != LBM_F32 && storage != LBM_F16DEV && storage != LBM_F32RAW)
-        return fail(LBM_E_UNSUPPORTED, "lbm_batch_create: batched storage must be F32, F16DEV or F32RAW");
+    if (storage != LBM_F32 && storage != LBM_F16DEV && storage != LBM_F32RAW && storage != LBM_F32SR)
+        return fail(LBM_E_UNSUPPORTED,
+                    "lbm_batch_create: batched storage must be F32, F16DEV, F32RAW or F32SR");
     auto *b = new Batch();
     b->max_slots = max_slots;
     b->st = (Storage)storage;
@@ -538,7 +567,8 @@ extern "C" int lbm_batch_create(int max_slots, int storage, void *pool, size_t p
     b->stream = (hipStream_t)stream;
     b->off_desc = 0;
     b->off_tabs = al(sizeof(SlotDesc) * max_slots);
-    b->off_counter = b->off_tabs + al(sizeof(PairTable<float>) * kBatchSets);
+    // the tables in the precision of the batch's collision
+    b->off_counter = b->off_tabs + al(sizeof(PairTable<double>) * kBatchSets);
     b->off_active = b->off_counter + kAl;
     b->off_heap = b->off_active + al(sizeof(int) * max_slots);
     if (b->off_heap >= pool_bytes) {
@@ -605,7 +635,9 @@ extern "C" int lbm_batch_submit(lbm_batch_t *h, const lbm_dvm_t *dvm, const lbm_
     Req r{};
     lbm_params_t par;
     PairTable<float> tab;
+    PairTable<double> tabd;
     int rc = problem_params(d, *prob, par, &tab, &r.sc, false);
+    if (rc == LBM_OK && b.st == Storage::F32SR) rc = problem_params(d, *prob, par, &tabd, &r.scd, true);
     if (rc) return rc;
     if (r.sc.halo > 4) return fail(LBM_E_UNSUPPORTED, "lbm_batch_submit: wall halo above 4");
     if (b.tab_set[set]) {
@@ -615,8 +647,12 @@ extern "C" int lbm_batch_submit(lbm_batch_t *h, const lbm_dvm_t *dvm, const lbm_
     } else {
         b.tabs[set] = tab;
         b.tab_set[set] = true;
-        hipError_t e = hipMemcpy(b.pool + b.off_tabs + sizeof(PairTable<float>) * set, &tab,
-                                 sizeof(tab), hipMemcpyHostToDevice);
+        hipError_t e =
+            b.st == Storage::F32SR
+                ? hipMemcpy(b.pool + b.off_tabs + sizeof(PairTable<double>) * set, &tabd,
+                            sizeof(tabd), hipMemcpyHostToDevice)
+                : hipMemcpy(b.pool + b.off_tabs + sizeof(PairTable<float>) * set, &tab,
+                            sizeof(tab), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_ok(e, "lbm_batch_submit: table upload");
     }
     r.id = req_id;

@@ -47,6 +47,11 @@ struct St<Storage::F16DEV> {
     using T = _Float16;
     using R = float;
 };
+template <>
+struct St<Storage::F32SR> {
+    using T = float;
+    using R = double;
+};
 
 // PCG-family integer hash (Jarzynski & Olano, "Hash Functions for GPU
 // Rendering", JCGT 2020): one 32-bit output per 32-bit input.
@@ -67,20 +72,32 @@ __device__ __forceinline__ _Float16 sr_half(float x, uint32_t rnd) {
     return v[0];
 }
 
+// Stochastic rounding of a double to float on the magnitude: the 29 mantissa
+// bits below float precision get 29 random bits added and are then cleared,
+// so the magnitude rounds up with a probability equal to the dropped fraction
+// (unbiased), and the cleared double converts to float exactly (normal range).
+__device__ __forceinline__ float sr_float(double x, uint32_t rnd) {
+    uint64_t b = (uint64_t)__double_as_longlong(x);
+    b += (uint64_t)(rnd >> 3);
+    b &= ~((uint64_t(1) << 29) - 1);
+    return (float)__longlong_as_double((long long)b);
+}
+
 template <Storage S>
 __device__ __forceinline__ typename St<S>::R decode_dev(typename St<S>::T v,
                                                          typename St<S>::R wr0) {
     using R = typename St<S>::R;
     if constexpr (S == Storage::F16DEV)
         return wr0 * (R)v;
-    else if constexpr (S == Storage::F32)
-        return v;
+    else if constexpr (S == Storage::F32 || S == Storage::F32SR)
+        return (R)v;
     else
         return (R)v - wr0;
 }
 
-// SRND selects stochastic rounding for half storage (time steps); init and
-// import round to nearest so that an exported state re-imports bit-exactly.
+// SRND selects stochastic rounding for the half and the FP32SR storages (time
+// steps); init and import round to nearest so that an exported state
+// re-imports bit-exactly.
 template <Storage S, bool SRND>
 __device__ __forceinline__ typename St<S>::T encode_dev(typename St<S>::R d,
                                                          typename St<S>::R wr0,
@@ -91,7 +108,9 @@ __device__ __forceinline__ typename St<S>::T encode_dev(typename St<S>::R d,
         return sr_half(d * inv_wr0, rnd);
     else if constexpr (S == Storage::F16DEV)
         return (T)(d * inv_wr0);
-    else if constexpr (S == Storage::F32)
+    else if constexpr (S == Storage::F32SR && SRND)
+        return sr_float(d, rnd);
+    else if constexpr (S == Storage::F32 || S == Storage::F32SR)
         return (T)d;
     else
         return (T)(d + wr0);
@@ -102,7 +121,7 @@ template <Storage S>
 __device__ __forceinline__ double stored_value(typename St<S>::T v, double wrd) {
     if constexpr (S == Storage::F16DEV)
         return wrd * (1.0 + (double)(float)v * (1.0 / kF16Scale));
-    else if constexpr (S == Storage::F32)
+    else if constexpr (S == Storage::F32 || S == Storage::F32SR)
         return wrd + (double)v;
     else
         return (double)v;
@@ -209,9 +228,9 @@ __device__ __forceinline__ R lin3(R x, R y, R z) {
         return addk<C>(addk<B>(mulk<A>(x), y), z);
 }
 
-// Encode all velocities of one node. Stochastic rounding (half storage in time
-// steps) takes one PCG hash of (node, step) and gives slot alpha the top 13
-// bits of key + alpha * 0x9E3779B9, a Weyl sequence with the golden-ratio
+// Encode all velocities of one node. Stochastic rounding (time steps of the
+// half and FP32SR storages) takes one PCG hash of (node, step) and gives slot
+// alpha the top bits (13 for half, 29 for FP32SR) of key + alpha * 0x9E3779B9, a Weyl sequence with the golden-ratio
 // increment: each offset is uniform, and the offsets of one node are evenly
 // spread rather than independent, which keeps a node's rounding errors from
 // adding up. Two operations per slot instead of a hash per slot.
@@ -221,7 +240,7 @@ __device__ __forceinline__ void encode_all(const typename St<S>::R (&d)[SET::V],
                                            uint32_t step, typename St<S>::T (&v)[SET::V]) {
     constexpr int NR = SET::NR;
     uint32_t key = 0;
-    if constexpr (S == Storage::F16DEV && SRND) key = node_key(n, step);
+    if constexpr (stochastic_storage(S) && SRND) key = node_key(n, step);
     auto rnd = [&](int slot) -> uint32_t { return key + (uint32_t)slot * 0x9E3779B9u; };
     if constexpr (NR) v[0] = encode_dev<S, SRND>(d[0], t.wr00, t.inv_wr00, rnd(0));
     for_pairs<SET::NP>([&](auto pc) {

@@ -67,7 +67,20 @@ struct StepScalars {
     int64_t nodes;
 };
 
-enum class Storage : int { F64 = LBM_F64, F32 = LBM_F32, F16DEV = LBM_F16DEV, F32RAW = LBM_F32RAW };
+enum class Storage : int {
+    F64 = LBM_F64,
+    F32 = LBM_F32,
+    F16DEV = LBM_F16DEV,
+    F32RAW = LBM_F32RAW,
+    F32SR = LBM_F32SR
+};
+
+// Storages whose stored values are deviations from w rho0, and whose rounding
+// is stochastic (keyed on node and step).
+constexpr bool deviation_storage(Storage s) {
+    return s == Storage::F32 || s == Storage::F16DEV || s == Storage::F32SR;
+}
+constexpr bool stochastic_storage(Storage s) { return s == Storage::F16DEV || s == Storage::F32SR; }
 
 // Layouts of the population array of a solve.
 //   kDirect   : node x holds its own post-collision populations, velocity alpha

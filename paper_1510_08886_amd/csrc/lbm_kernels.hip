@@ -812,9 +812,13 @@ struct L2 {
         {SET::ID, Storage::F32RAW, &L2<SET, Storage::F32RAW>::table},         \
         {SET::ID, Storage::F16DEV, &L2<SET, Storage::F16DEV>::table}
 
+// FP32 deviations collided in FP64 with stochastic rounding: the channel sets
+#define LBM_2D_SR(SET) {SET::ID, Storage::F32SR, &L2<SET, Storage::F32SR>::table}
+
 const Launch *find_launch_2d(int set_id, Storage st) {
     static const Entry entries[] = {
         LBM_2D(SetD2V17), LBM_2D(SetD2V37), LBM_2D(SetD2V16), LBM_2D(SetD2V33), LBM_2D(SetD2V32),
+        LBM_2D_SR(SetD2V17), LBM_2D_SR(SetD2V37),
     };
     for (const auto &e : entries)
         if (e.id == set_id && e.s == st) return e.l;

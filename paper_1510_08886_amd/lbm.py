@@ -19,7 +19,7 @@ LBM_OK = 0
 LBM_E_UNSUPPORTED = -2
 ERRORS = {-1: "LBM_E_INVALID", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_NO_MEMORY",
           -4: "LBM_E_QUADRATURE", -5: "LBM_E_DEVICE", -6: "LBM_E_NOT_CONVERGED"}
-STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "f32raw": 3}
+STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "f32raw": 3, "f32sr": 4}
 LAYOUT = {"auto": 0, "in_place": 1, "ping_pong": 2}
 
 # Velocity groups of the three models used for channels and ducts: generators,

@@ -144,6 +144,17 @@ def test_state_bytes_layout():
     pop16, _ = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
                                               storage="f16dev"))
     assert pop16 == pop // 2
+    pop_sr, _ = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
+                                               storage="f32sr"))
+    assert pop_sr == pop             # the same FP32 deviations, collided in FP64
+
+
+def test_unknown_storage_is_refused():
+    d = lbm.Dvm.named("D2V37")
+    pc = lbm.Problem(dim=2, nx=16, ny=8, kn=0.1, hermite_order=4).to_c()
+    pc.storage = 5
+    pop, scr = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lbm.lib().lbm_state_bytes(d._h, ctypes.byref(pc), ctypes.byref(pop), ctypes.byref(scr)) == -1
 
 
 def test_state_bytes_in_place_up_to_512_mib_then_two_copies():

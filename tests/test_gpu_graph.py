@@ -69,10 +69,11 @@ def test_graph_replay_matches_one_launch_per_step(name, N, nx, ny, nz, storage):
     b.close()
 
 
-def test_graph_replay_default_and_fp16():
+@pytest.mark.parametrize("storage", ["f16dev", "f32sr"])
+def test_graph_replay_default_and_fp16(storage):
     from paper_1510_08886_amd import lbm
     d = lbm.Dvm.named("D2V37")
-    prob = lbm.Problem(dim=2, nx=64, ny=12, kn=0.1, hermite_order=4, storage="f16dev")
+    prob = lbm.Problem(dim=2, nx=64, ny=12, kn=0.1, hermite_order=4, storage=storage)
     s = lbm.Solver(d, prob).init()
     with pytest.raises(lbm.LbmError):
         s.set_graph_steps(8)       # stochastic rounding keys on the step counter
@@ -119,6 +120,7 @@ def test_graph_cache_eviction_and_teardown_in_flight():
     ("D2V17", 3, 1, 40, "f64"),      # the launch-bound FP64 channel
     ("D2V37", 4, 20, 12, "f32"),     # 240 nodes, wall rows on both sides
     ("D2V37", 4, 16, 16, "f16dev"),  # 256 nodes; stochastic rounding numbered per step
+    ("D2V17", 3, 1, 40, "f32sr"),    # FP64 collision, FP32 stochastic rounding per step
     ("D2V37", 5, 1, 21, "f32"),      # Hermite order 5 variant
     ("D2V32", 4, 5, 29, "f64"),      # halo 12, periodic wraps
 ])

@@ -386,7 +386,7 @@ def test_converged_golden_files_match_recipes_and_oracle():
             assert (g["dvm"], g["ny"], g["kn"]) == (name, ny, kn)
             assert g["stop"] is not None
             steps = sorted(g["mdot"])
-            assert steps[-1] == g["stop"] + mcg.WINDOW_AFTER
+            assert steps[0] == mcg.CHECK and steps[-1] == g["stop"] + mcg.WINDOW_AFTER
             assert all(b - a == mcg.CHECK for a, b in zip(steps, steps[1:]))
             m = g["mdot"]
             # the stop is the first stored check meeting the tolerance
@@ -401,3 +401,28 @@ def test_converged_golden_files_match_recipes_and_oracle():
                                  N=mcg.N_OF[g["dvm"]]).init()
         o.run(s0)
         assert abs(o.observe()["mdot"] - g["mdot"][s0]) <= 1e-14 * abs(g["mdot"][s0])
+
+
+def test_throughput_golden_file_matches_recipe():
+    """The stored 1000-step oracle run of the 2048 x 512 throughput channel
+    (tests/golden/throughput_d2v37.txt): its mass is the seeded density's
+    sum at every check (exact conservation), the mass flow grows from rest,
+    the row-averaged u_x is near mirror-symmetric (exactly so but for the 1e-3
+    random density) and non-slip (u_x > 0 at the wall rows), and the stored
+    columns' densities are the seeded ones up to O(Ma) changes."""
+    import lbm_workloads as wl
+    from tests.test_gpu_parity import _throughput_golden
+    c = wl.THROUGHPUT_D2V37
+    g = _throughput_golden()
+    rho0 = wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"])
+    assert g["steps"] == c["steps"] and sorted(g["mdot"]) == list(range(100, 1001, 100))
+    for step, (md, mass) in g["mdot"].items():
+        assert abs(mass - rho0.sum()) <= 1e-12 * rho0.sum(), step
+    mds = [g["mdot"][k][0] for k in sorted(g["mdot"])]
+    assert all(b > a > 0 for a, b in zip(mds, mds[1:]))
+    ux = np.array([g["uxrow"][j] for j in range(c["ny"])])
+    assert np.max(np.abs(ux - ux[::-1])) <= 1e-2 * np.max(ux)
+    assert ux[0] > 0 and ux[-1] > 0
+    r0 = rho0.reshape(c["ny"], c["nx"])
+    for (i, j), (rho, _, _) in g["col"].items():
+        assert abs(rho - r0[j, i]) <= 5e-3
