@@ -309,7 +309,7 @@ def serving_block(n_plain: int):
     for k, g in gold.items():
         assert (trace[k]["ny"], trace[k]["kn"], trace[k]["dvm"]) == (g["ny"], g["kn"], g["dvm"])
         errs.append(rel_err_at(g, by_id[k]["steps"], by_id[k]["mdot"]))
-    sustainable, rows = serve.rate_sweep(lambda r: trace_at(r, 800), (200, 400, 800, 1200),
+    sustainable, rows = serve.rate_sweep(lambda r: trace_at(r, 800), (200, 300, 400, 800),
                                          quantum=quantum, **kw)
     return {
         "workload": "1000 requests, Poisson 200/s, Ny~U[16,1024], Kn log-uniform [0.01,1], "
