@@ -600,6 +600,15 @@ def main():
     bytes_per_launch = 2 * d.V * 4 * nodes         # each population read once, written once
     achieved = bytes_per_launch / (ms * 1e-3 / args.steps) / 1e9
     obs = s.observe()
+    # stability: five more timed blocks of the same length after the timed
+    # region (not part of value)
+    reps = []
+    for _ in range(5):
+        e0.record(stream)
+        s.run(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) / args.steps)
     s.close()
     parity = None if args.no_parity else throughput_parity(d, prob)
     rec = profile_record()
@@ -640,6 +649,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "wall_s": round(wall, 3),
+        "repeat_ms_per_step": {"blocks": [round(x, 5) for x in reps],
+                               "median": round(sorted(reps)[2], 5),
+                               "note": "five more blocks of the same step count after the "
+                                       "timed region (HIP events), for its spread"},
         "mdot_after": obs["mdot"],
         "parity_vs_oracle": parity,
     }
