@@ -120,3 +120,34 @@ def test_counts_are_recorded():
     counts = {n: len(models(n)) for n in SETS}
     assert all(v > 0 for v in counts.values())
     print("enumerated counts:", counts)
+
+
+@pytest.mark.parametrize("name", ["S5", "S6", "S7", "S1"])
+def test_enumerated_models_are_quadratures_by_the_oracle(name):
+    """A seeded sample of each enumerated set, checked with the oracle's own
+    code (independent of the library): the velocities integrate every monomial
+    of degree <= Q exactly (Eqs. genQua / orth), the weights are positive, V
+    and E are those of the expanded stencil, and the oracle's nullity condition
+    (Eq. dimker) has a root at the enumerated c* with the same weights."""
+    import numpy as np
+
+    from oracle import dvm as odvm
+    dim, Q, emax, scat, _, _ = SETS[name]
+    ms = models(name)
+    rng = np.random.default_rng(1510)
+    pick = [ms[int(k)] for k in rng.choice(len(ms), size=min(6, len(ms)), replace=False)]
+    for m in pick:
+        gens = [tuple(int(x) for x in g) for g in m["gens"]]
+        d = odvm.make_dvm(dim, gens, m["weights"], m["c"], Q)
+        assert d.V == m["V"] and d.energy == m["E"]
+        assert all(w > 0 for w in m["weights"])
+        for deg in range(1, Q + 1):
+            assert odvm.quadrature_errors(d, deg) < 1e-10, (m, deg)
+        if scat:
+            assert all(0 not in e for e in d.velocities.tolist())
+        roots = odvm.solve_roots(dim, gens, Q, 0.995 * m["c"], 1.005 * m["c"], n_scan=400)
+        near = [r for r in roots if abs(float(r[0]) - m["c"]) <= 1e-9 * m["c"]]
+        assert len(near) == 1, (m, [float(r[0]) for r in roots])
+        wbar = [float(x) for x in near[0][1]]
+        for a, b in zip(wbar, m["weights"]):
+            assert abs(a - b) <= 1e-9 * abs(b), (m, wbar)
