@@ -286,12 +286,16 @@ int lbm_solver_set_resident_steps(lbm_solver_t *s, int max_steps);
  * results are bit for bit those of one launch per step. on = 0 switches it
  * off; band_rows is the height of each workgroup's band of rows (0: chosen
  * for the device). on = 1 alternates the two steps in all waves of a
- * workgroup; on = 2 gives them to producer and consumer waves that overlap.
- * Compiled for the 2D sets reaching at most 4 nodes. Default 2 for
- * ping-pong problems that are not graph-replayed, in FP64 and FP32 storage;
- * 0 otherwise (FP16 deviations: their single step is bound by its arithmetic).
- * LBM_E_UNSUPPORTED for on != 0 where not compiled. lbm_run takes two-step
- * launches while two or more steps remain. */
+ * workgroup; on = 2 gives them to producer and consumer waves that overlap;
+ * on = 3 splits the producers into two groups that take alternate chunks of
+ * rows, so that one group's HBM reads are in flight while the other
+ * computes. Compiled for the 2D sets reaching at most 4 nodes. Default 3
+ * (2 where mode 3's chunks of rows are more than one row shorter than mode
+ * 2's, as for D2V17 in FP32) for ping-pong problems that are not
+ * graph-replayed, in FP64 and FP32 storage; 0 otherwise (FP16 deviations:
+ * their single step is bound by its arithmetic). LBM_E_UNSUPPORTED for
+ * on != 0 where not compiled. lbm_run takes two-step launches while two or
+ * more steps remain. */
 int lbm_solver_set_pair_steps(lbm_solver_t *s, int on, int band_rows);
 
 /* Longest step sequence lbm_run replays from one captured HIP graph

@@ -202,7 +202,7 @@ struct Solver {
     // Most steps per one-workgroup resident launch (0: off; see lbm_run).
     int resident_steps = 0;
     // Two ping-pong steps per launch (Launch::pair) and its band height (0: auto).
-    int pair_steps = 0;             // 0 off, 1 one workgroup per CU, 2 two per CU
+    int pair_steps = 0;             // 0 off, else the lbm_solver_set_pair_steps mode (1-3)
     int pair_band_rows = 0;
     ~Solver() {
         if (!graphs.empty() || capture) (void)hipStreamSynchronize(stream);
@@ -454,13 +454,16 @@ int lbm::solver_create(const lbm_dvm_t *dvm, const lbm_problem_t *prob, void *po
         (graphs && !stochastic_storage(st) && L.copy_bytes <= kGraphMaxBytes) ? kGraphMaxSteps : 0;
     s->graphs_allowed = graphs;
     s->resident_steps = resident_ok(*s) ? kResidentMaxSteps : 0;
-    // two steps per launch for ping-pong problems not stepped from graphs,
-    // producer and consumer waves (mode 2). Measured on MI355X, D2V37 FP32
-    // 4096 x 2048 (1.24 GB per copy): 303 us per step against 437 us for one
-    // launch per step. FP16 deviations keep single steps: their step is
-    // bound by its arithmetic (252 against 319 us); so do FP32SR's (FP64
-    // collision).
-    s->pair_steps = (pair_ok(*s) && s->graph_steps == 0 && !stochastic_storage(st)) ? 2 : 0;
+    // two steps per launch for ping-pong problems not stepped from graphs:
+    // two producer groups and consumer waves (mode 3) where the kernel table
+    // prefers them, else one producer group (mode 2). Measured on MI355X,
+    // D2V37 FP32 4096 x 2048 (1.24 GB per copy): 230 us per step (mode 3) and
+    // 269 us (mode 2) against 437 us for one launch per step. FP16 deviations
+    // keep single steps: their step is bound by its arithmetic (252 against
+    // 319 us); so do FP32SR's (FP64 collision).
+    s->pair_steps = (pair_ok(*s) && s->graph_steps == 0 && !stochastic_storage(st))
+                        ? (s->L->pair_twin_default ? 3 : 2)
+                        : 0;
     if (st == Storage::F64 || st == Storage::F32SR)
         fill_tables<double>(d, *prob, s->par, s->tab, s->sc);
     else
@@ -633,12 +636,15 @@ extern "C" int lbm_solver_set_resident_steps(lbm_solver_t *h, int max_steps) {
 }
 
 extern "C" int lbm_solver_set_pair_steps(lbm_solver_t *h, int on, int band_rows) {
-    if (!h || band_rows < 0 || on < 0 || on > 2)
+    if (!h || band_rows < 0 || on < 0 || on > 3)
         return fail(LBM_E_INVALID, "lbm_solver_set_pair_steps: bad arguments");
     Solver &s = *reinterpret_cast<Solver *>(h);
     if (on && !pair_ok(s))
         return fail(LBM_E_UNSUPPORTED,
                     "two steps per launch: 2D ping-pong problems of a set with a compiled kernel");
+    if (on == 3 && !s.L->pair_twin)
+        return fail(LBM_E_UNSUPPORTED,
+                    "two steps per launch: the two producer groups' ring does not fit the LDS");
     s.pair_steps = on;
     s.pair_band_rows = band_rows;
     return LBM_OK;

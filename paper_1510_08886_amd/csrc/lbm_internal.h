@@ -129,6 +129,10 @@ struct Launch {
     // compiled). band_rows = rows per workgroup band (0: chosen for the chip).
     int (*pair)(const StepBuffers &, const void *tab, const void *sc, hipStream_t, uint32_t step,
                 int band_rows, int mode);
+    // whether pair() has the two-producer-group schedule (mode 3), and
+    // whether it is the default two-step schedule (else mode 2)
+    bool pair_twin = false;
+    bool pair_twin_default = false;
 };
 
 // Channel stencils reaching at least this far (max |e_i|, the set's halo) use

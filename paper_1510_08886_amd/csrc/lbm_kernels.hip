@@ -330,36 +330,54 @@ __global__ __launch_bounds__(256) void k_run2d(StepBuffers b, PairTable<typename
 //     wait ends. Each wait is also bounded: one that gives up raises a flag in
 //     device memory (read by the host at the next observation) and its wave
 //     leaves, and so, in turn, does the other group's.
-enum PairKind : int { kPairAlternate = 1, kPairSplit = 2 };
+//   kPairTwin: as kPairSplit, with two producer groups that take the even and
+//     the odd chunks. A producer gathers and collides its chunk before it
+//     waits for the ring rows to be free, and only its ring writes wait, so
+//     the gather of one group is in flight while the other computes: with a
+//     single group each chunk's HBM latency lies on the critical path. Chunks
+//     of fewer rows keep the waves at three per SIMD, the register budget of
+//     the single-group form.
+enum PairKind : int { kPairAlternate = 1, kPairSplit = 2, kPairTwin = 3 };
 
 template <class SET, typename T, int KIND>
 struct PairTile {
     static constexpr int H = SET::H, HN = SET::HN, V = SET::V;
     static constexpr size_t kLds = 156 * 1024;     // of the 160 KB of a gfx950 CU
     // ring rows for chunks of rr rows
-    static constexpr int ring_rows(int rr) { return (KIND == kPairSplit ? 2 : 1) * rr + 2 * HN; }
+    static constexpr int ring_rows(int rr) { return (KIND == kPairAlternate ? 1 : 2) * rr + 2 * HN; }
     static constexpr size_t bytes(int bx, int rr) {
         return (size_t)ring_rows(rr) * (bx + 2 * H) * V * sizeof(T) + (size_t)2 * HN * bx * 8;
     }
     static constexpr int up64(int x) { return (x + 63) / 64 * 64; }
-    // threads: one step-t node of a chunk each (split: plus one step-(t+1)
-    // node of a chunk each, in waves of their own)
+    // threads: one step-t node of a chunk each (per producer group) and, for
+    // the split kinds, one step-(t+1) node of a chunk each, in waves of their
+    // own
     static constexpr int threads(int bx, int rr) {
-        return up64(rr * (bx + 2 * H)) + (KIND == kPairSplit ? up64(rr * bx) : 0);
+        return up64(rr * (bx + 2 * H)) * (KIND == kPairTwin ? 2 : 1) +
+               (KIND == kPairAlternate ? 0 : up64(rr * bx));
     }
-    static constexpr bool fits(int bx, int rr) { return bytes(bx, rr) <= kLds && threads(bx, rr) <= 1024; }
-    static constexpr int pick_bx() { return fits(64, KIND == kPairSplit ? 4 : 8) ? 64 : 32; }
+    // kPairTwin: at most three waves per SIMD (12 per CU), so that each wave
+    // keeps 168 VGPRs
+    static constexpr int kMaxThreads = KIND == kPairTwin ? 768 : 1024;
+    static constexpr bool fits(int bx, int rr) {
+        return bytes(bx, rr) <= kLds && threads(bx, rr) <= kMaxThreads;
+    }
+    static constexpr int pick_bx() {
+        return fits(64, KIND == kPairAlternate ? 8 : KIND == kPairSplit ? 4 : 3) ? 64 : 32;
+    }
     static constexpr int pick_rr(int bx) {
-        return fits(bx, 16) ? 16 : fits(bx, 8) ? 8 : fits(bx, 6) ? 6 : fits(bx, 4) ? 4 : 2;
+        return fits(bx, 16) ? 16 : fits(bx, 8) ? 8 : fits(bx, 6) ? 6 : fits(bx, 4) ? 4
+               : (KIND == kPairTwin && fits(bx, 3)) ? 3 : 2;
     }
     static constexpr int BX = pick_bx();
     static constexpr int RR = pick_rr(BX);
     static constexpr int EW = BX + 2 * H;          // ring row pitch (columns)
     static constexpr int RING = ring_rows(RR);
     static constexpr bool ok = fits(BX, RR) && H <= 4;
-    static constexpr int PT = up64(RR * EW);
-    static constexpr int CT = KIND == kPairSplit ? up64(RR * BX) : 0;
-    static constexpr int NT = PT + CT;
+    static constexpr int PT = up64(RR * EW);       // threads of one producer group
+    static constexpr int NPG = KIND == kPairTwin ? 2 : 1;
+    static constexpr int CT = KIND == kPairAlternate ? 0 : up64(RR * BX);
+    static constexpr int NT = NPG * PT + CT;
 };
 
 // bound of one wait on the other group (~0.5 s): only a broken schedule reaches it
@@ -388,7 +406,9 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
     constexpr int BX = TL::BX, RR = TL::RR, EW = TL::EW, RING = TL::RING;
     __shared__ T ring[RING * V * EW];      // [row mod RING][alpha][column]
     __shared__ double ap[2 * HN * BX];     // step-t partials of the tile's columns [face][row][col]
-    __shared__ int produced, consumed;     // kPairSplit: waves done per group, summed over chunks
+    // split kinds: waves done per group, summed over the group's chunks
+    // (kPairTwin: produced[g] for the producer group of the chunks k = g mod 2)
+    __shared__ int produced[2], consumed;
 
     // tile of this workgroup: XCD x (workgroups go to the 8 XCDs round-robin)
     // takes a contiguous run of tiles in (band, strip) order, so the strips
@@ -411,8 +431,10 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
         return x >= RING ? x - RING : x;
     };
     // step t of rows [lo, hi), columns x0 - H .. x0 + ncols + H - 1, into the
-    // ring; threads tid, tid + nth, ...
-    auto first = [&](int lo, int hi, int tid, int nth) {
+    // ring; threads tid, tid + nth, ... Each node is gathered and collided
+    // first; gate() is called before its results go to LDS (kPairTwin: the
+    // wait for the ring rows to be free). False when a gate gave up.
+    auto first = [&](int lo, int hi, int tid, int nth, auto gate) -> bool {
         const int w = ncols + 2 * H;
         const int n1 = (hi - lo) * w;
         const int sl = (lo - a) % RING;
@@ -431,12 +453,15 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
             relax2d<SET, R, N5>(d, t, s, t.c);
             T v[V];
             encode_all<SET, S, true>(d, t, n, step, v);
+            if (!gate()) return false;
             T *rw = ring + slot_from(sl, lo, j) * (V * EW) + c;
 #pragma unroll
             for (int q = 0; q < V; ++q) rw[q * EW] = v[q];
             if (c >= H && c < H + ncols) wall_partials2d_col<SET, S>(v, t, s, j, ap + (c - H), BX);
         }
+        return true;
     };
+    auto open = [] { return true; };
     // step t + 1 of rows [lo, hi), the tile's own columns, from the ring to HBM
     auto second = [&](int lo, int hi, int tid, int nth) {
         const int n2 = (hi - lo) * BX;
@@ -482,37 +507,50 @@ void k_pair2d(StepBuffers b, PairTable<typename St<S>::R> t, StepScalars<typenam
 
     if constexpr (KIND == kPairAlternate) {
         for (int k = 0; k < chunks; ++k) {
-            first(k == 0 ? a : need(k - 1), need(k), threadIdx.x, blockDim.x);
+            first(k == 0 ? a : need(k - 1), need(k), threadIdx.x, blockDim.x, open);
             __syncthreads();
             second(y0 + k * RR, min(y0 + (k + 1) * RR, y1), threadIdx.x, blockDim.x);
             __syncthreads();
         }
     } else {
-        static_assert(TL::PT + TL::CT <= 1024, "producer and consumer waves fit one workgroup");
-        constexpr int PW = TL::PT / 64, CW = TL::CT / 64;
+        static_assert(TL::NT <= TL::kMaxThreads, "producer and consumer waves fit one workgroup");
+        constexpr int PW = TL::PT / 64, CW = TL::CT / 64, NPG = TL::NPG;
         if (threadIdx.x == 0) {
-            produced = 0;
+            produced[0] = 0;
+            produced[1] = 0;
             consumed = 0;
         }
         __syncthreads();
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        // A wave counts chunk k only once every wave of its group has counted
-        // chunk k - 1, so produced >= PW (k + 1) means that all producer
-        // waves have finished chunk k (a fast wave cannot stand in for a slow
-        // one), and likewise for consumed.
-        if (wave < PW) {
-            // producer: chunk k overwrites the ring rows of chunk k - 2
-            for (int k = 0; k < chunks; ++k) {
-                if (k >= 2 && !pair_wait(&consumed, CW * (k - 1), b.err)) return;
-                first(k == 0 ? a : need(k - 1), need(k), threadIdx.x, TL::PT);
-                if (!pair_wait(&produced, PW * k, b.err)) return;
+        // Chunk k is produced by group g = k mod NPG, as that group's
+        // (k / NPG)-th chunk. A wave counts a chunk of its group only once
+        // every wave of the group has counted the group's previous chunk, so
+        // produced[g] >= PW (m + 1) means that all waves of group g have
+        // finished the group's m-th chunk (a fast wave cannot stand in for a
+        // slow one), and likewise for consumed.
+        if (wave < NPG * PW) {
+            const int g = wave / PW;
+            const int tid = threadIdx.x - g * TL::PT;
+            // chunk k overwrites the ring rows of chunk k - 2
+            for (int k = g; k < chunks; k += NPG) {
+                const int lo = k == 0 ? a : need(k - 1);
+                bool ok;
+                if constexpr (KIND == kPairTwin) {
+                    // gather and collide first; only the ring writes wait
+                    ok = first(lo, need(k), tid, TL::PT,
+                               [&] { return k < 2 || pair_wait(&consumed, CW * (k - 1), b.err); });
+                } else {
+                    ok = k < 2 || pair_wait(&consumed, CW * (k - 1), b.err);
+                    if (ok) ok = first(lo, need(k), tid, TL::PT, open);
+                }
+                if (!ok || !pair_wait(&produced[g], PW * (k / NPG), b.err)) return;
                 if (lane == 0)
-                    __hip_atomic_fetch_add(&produced, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(&produced[g], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         } else {
             for (int k = 0; k < chunks; ++k) {
-                if (!pair_wait(&produced, PW * (k + 1), b.err)) return;
-                second(y0 + k * RR, min(y0 + (k + 1) * RR, y1), threadIdx.x - TL::PT, TL::CT);
+                if (!pair_wait(&produced[k % NPG], PW * (k / NPG + 1), b.err)) return;
+                second(y0 + k * RR, min(y0 + (k + 1) * RR, y1), threadIdx.x - NPG * TL::PT, TL::CT);
                 if (!pair_wait(&consumed, CW * k, b.err)) return;
                 if (lane == 0)
                     __hip_atomic_fetch_add(&consumed, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -657,6 +695,18 @@ __global__ __launch_bounds__(256) void k_export2d(const void *pop, int layout, d
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Default two-step schedule: two producer groups unless their chunks are
+// more than one row shorter than the single group's. Measured on MI355X, 200
+// steps per ping-pong copy above the cache (us per step, mode 2 -> mode 3):
+// D2V37 FP32 4096 x 2048 (chunks of 4 -> 3 rows) 269 -> 230, D2V37 FP64
+// 2048 x 1024 (4 -> 4) 147 -> 136, D2V17 FP32 4096 x 4096 (6 -> 3) 250 -> 268.
+template <class SET, typename T>
+constexpr bool pair_twin_default() {
+    using TW = PairTile<SET, T, kPairTwin>;
+    using SP = PairTile<SET, T, kPairSplit>;
+    return TW::ok && (!SP::ok || TW::RR + 1 >= SP::RR);
+}
+
 template <class SET, Storage S>
 struct L2 {
     using R = typename St<S>::R;
@@ -790,20 +840,24 @@ struct L2 {
             return hip_ok(hipGetLastError(), "two-step kernel launch");
         }
     }
-    // mode 1: alternating phases; mode 2: producer and consumer waves
+    // mode 1: alternating phases; mode 2: producer and consumer waves; mode
+    // 3: two producer groups and consumer waves
     static int pair(const StepBuffers &b, const void *tab, const void *sc, hipStream_t st,
                     uint32_t stp, int band_rows, int mode) {
         const auto &t = *(const PairTable<R> *)tab;
         const auto &s = *(const StepScalars<R> *)sc;
         if (b.layout != kDirect || !b.pop_out)
             return fail(LBM_E_INVALID, "two-step kernel: needs two population copies");
-        return mode == 2 ? pair_launch<kPairSplit>(b, t, s, st, stp, band_rows)
-                         : pair_launch<kPairAlternate>(b, t, s, st, stp, band_rows);
+        return mode == 3   ? pair_launch<kPairTwin>(b, t, s, st, stp, band_rows)
+               : mode == 2 ? pair_launch<kPairSplit>(b, t, s, st, stp, band_rows)
+                           : pair_launch<kPairAlternate>(b, t, s, st, stp, band_rows);
     }
     static constexpr Launch table{&step,    &init,         &observe, &exportp,
                                   &importp, &run_resident,
                                   PairTile<SET, typename St<S>::T, kPairAlternate>::ok ? &pair
-                                                                                    : nullptr};
+                                                                                    : nullptr,
+                                  PairTile<SET, typename St<S>::T, kPairTwin>::ok,
+                                  pair_twin_default<SET, typename St<S>::T>()};
 };
 
 #define LBM_2D(SET)                                                           \

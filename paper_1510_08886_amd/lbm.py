@@ -16,7 +16,12 @@ PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "liblbmdvm.so"
 
 LBM_OK = 0
+LBM_E_INVALID = -1
 LBM_E_UNSUPPORTED = -2
+LBM_E_NO_MEMORY = -3
+LBM_E_QUADRATURE = -4
+LBM_E_DEVICE = -5
+LBM_E_NOT_CONVERGED = -6
 ERRORS = {-1: "LBM_E_INVALID", -2: "LBM_E_UNSUPPORTED", -3: "LBM_E_NO_MEMORY",
           -4: "LBM_E_QUADRATURE", -5: "LBM_E_DEVICE", -6: "LBM_E_NOT_CONVERGED"}
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "f32raw": 3, "f32sr": 4}
@@ -412,8 +417,9 @@ class Solver:
 
     def set_pair_steps(self, on, band_rows: int = 0):
         """Two time steps per launch (2D ping-pong problems; bitwise the same
-        results): on = False/0 off, True/1 one workgroup per CU, 2 two per CU;
-        band_rows 0 lets the library choose."""
+        results): on = False/0 off; True/1 all waves alternate the two steps;
+        2 producer and consumer waves; 3 two producer groups on alternate
+        chunks and consumer waves; band_rows 0 lets the library choose."""
         check(lib().lbm_solver_set_pair_steps(self._h, int(on), int(band_rows)),
               "lbm_solver_set_pair_steps")
         return self

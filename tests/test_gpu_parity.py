@@ -374,11 +374,12 @@ def test_full_size_ping_pong_f16dev_4096x2048():
     ("D2V16", 4, 64, 9, 0),      # halo 4, no rest velocity, ny < 2 * halo
 ])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f32raw"])
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_pair_steps_equal_single_steps(name, N, nx, ny, band_rows, storage, mode):
     """Two steps per launch (the intermediate state in an LDS ring; mode 1:
     all waves alternate between the two steps, mode 2: producer and consumer
-    waves) against one launch per step:
+    waves, mode 3: two producer groups on alternate chunks and consumer waves)
+    against one launch per step:
     bit-identical populations after even and odd step counts (an odd count
     ends with one single step), on random states, for every storage; FP64 also
     element by element against the oracle."""
@@ -388,12 +389,12 @@ def test_pair_steps_equal_single_steps(name, N, nx, ny, band_rows, storage, mode
                         layout="ping_pong")
     _, b, _ = make_pair(name, N, nx, ny, kn=0.07, ma=2e-2, storage=storage, rho=rho, u=u,
                         layout="ping_pong")
-    a.set_graph_steps(0).set_pair_steps(mode, band_rows)
     b.set_graph_steps(0).set_pair_steps(False)
     try:
+        a.set_graph_steps(0).set_pair_steps(mode, band_rows)
         a.run(2)
     except lbm.LbmError as err:
-        assert mode == 2 and err.code == lbm.LBM_E_UNSUPPORTED
+        assert mode in (2, 3) and err.code == lbm.LBM_E_UNSUPPORTED
         pytest.skip("the producer/consumer ring of this set and storage does not fit the LDS")
     b.run(2)
     if storage == "f64":
@@ -408,6 +409,24 @@ def test_pair_steps_equal_single_steps(name, N, nx, ny, band_rows, storage, mode
             assert np.max(np.abs(pg - po)) <= 1e-14, steps
     ma, mb = a.observe(), b.observe()
     assert ma["mdot"] == mb["mdot"] and ma["mass"] == mb["mass"]
+
+
+def test_pair_steps_mode_validation():
+    """Modes 0-3 are accepted for a 2D ping-pong problem (the twin-producer
+    mode 3 is compiled for every set that has the two-step kernel); anything
+    else is LBM_E_INVALID, and in-place stepping refuses two-step launches."""
+    from paper_1510_08886_amd import lbm
+    d, a, _ = make_pair("D2V37", 4, 64, 9, storage="f32", layout="ping_pong")
+    for mode in (0, 1, 2, 3):
+        a.set_pair_steps(mode)
+    for mode in (4, -1):
+        with pytest.raises(lbm.LbmError) as e:
+            a.set_pair_steps(mode)
+        assert e.value.code == lbm.LBM_E_INVALID
+    _, b, _ = make_pair("D2V37", 4, 64, 9, storage="f32", layout="in_place")
+    with pytest.raises(lbm.LbmError) as e:
+        b.set_pair_steps(3)
+    assert e.value.code == lbm.LBM_E_UNSUPPORTED
 
 
 def test_pair_steps_full_size_channel():
@@ -476,7 +495,7 @@ def test_accommodation_low_precision(storage, tol_pop):
         assert np.max(np.abs(pg - po) / w) <= tol_pop, steps
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_accommodation_pair_steps(mode, storage):
     """Two steps per launch with specular partners taken from the LDS ring
@@ -525,7 +544,7 @@ def _throughput_golden():
     return g
 
 
-@pytest.mark.parametrize("layout,pair", [("auto", 0), ("ping_pong", 2)])
+@pytest.mark.parametrize("layout,pair", [("auto", 0), ("ping_pong", 2), ("ping_pong", 3)])
 def test_throughput_channel_1000_steps_against_oracle(layout, pair):
     """The 2048 x 512 D2V37 FP32 throughput channel, 1000 steps from the seeded
     density, against the stored FP64 oracle run (tests/golden/throughput_d2v37.txt):

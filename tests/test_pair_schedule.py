@@ -15,11 +15,11 @@ import numpy as np
 import pytest
 
 LDS_BUDGET = 156 * 1024
-ALTERNATE, SPLIT = 1, 2     # the kernel's two schedules
+ALTERNATE, SPLIT, TWIN = 1, 2, 3     # the kernel's three schedules
 
 
 def ring_rows(kind, rr, HN):
-    return (2 if kind == SPLIT else 1) * rr + 2 * HN
+    return (1 if kind == ALTERNATE else 2) * rr + 2 * HN
 
 
 def nbytes(V, H, HN, elem, bx, rr, kind):
@@ -31,19 +31,26 @@ def _up64(x):
 
 
 def _threads(H, bx, rr, kind):
-    return _up64(rr * (bx + 2 * H)), (_up64(rr * bx) if kind == SPLIT else 0)
+    """(producer threads, all groups; consumer threads)"""
+    groups = 2 if kind == TWIN else 1
+    return groups * _up64(rr * (bx + 2 * H)), (0 if kind == ALTERNATE else _up64(rr * bx))
+
+
+def max_threads(kind):
+    # two producer groups: at most three waves per SIMD, for the register budget
+    return 768 if kind == TWIN else 1024
 
 
 def tile_shape(V, H, HN, elem, kind=ALTERNATE):
     def fits(bx, rr):
         return (nbytes(V, H, HN, elem, bx, rr, kind) <= LDS_BUDGET
-                and sum(_threads(H, bx, rr, kind)) <= 1024)
+                and sum(_threads(H, bx, rr, kind)) <= max_threads(kind))
 
-    bx = 64 if fits(64, 4 if kind == SPLIT else 8) else 32
+    bx = 64 if fits(64, {ALTERNATE: 8, SPLIT: 4, TWIN: 3}[kind]) else 32
     for rr in (16, 8, 6, 4):
         if fits(bx, rr):
             return bx, rr
-    return bx, 2
+    return bx, (3 if kind == TWIN and fits(bx, 3) else 2)
 
 
 def threads(V, H, HN, elem, kind):
@@ -77,10 +84,10 @@ def emulate(nx, ny, V, H, HN, elem, band_rows, kind=ALTERNATE):
     consumer reads chunk k."""
     bx, rr = tile_shape(V, H, HN, elem, kind)
     if (nbytes(V, H, HN, elem, bx, rr, kind) > LDS_BUDGET or H > 4
-            or sum(_threads(H, bx, rr, kind)) > 1024):
+            or sum(_threads(H, bx, rr, kind)) > max_threads(kind)):
         return False     # not compiled (the library reports LBM_E_UNSUPPORTED)
     pt, ct = threads(V, H, HN, elem, kind)
-    assert pt + ct <= 1024
+    assert pt + ct <= max_threads(kind)
     ew, nring = bx + 2 * H, ring_rows(kind, rr, HN)
     nstrips, bands, band_rows = grid_of(nx, ny, bx, rr, band_rows)
     total = nstrips * bands
@@ -138,7 +145,9 @@ def emulate(nx, ny, V, H, HN, elem, band_rows, kind=ALTERNATE):
                 if j >= ny - HN:
                     assert all((1, r) in partial_rows for r in range(HN))
 
-        if kind == SPLIT:
+        if kind in (SPLIT, TWIN):
+            # (TWIN: the other producer group may write chunk k + 1 while
+            # chunk k is read, never chunk k + 2: its ring-write wait)
             if chunks:
                 produce(0)
             for k in range(chunks):
@@ -166,7 +175,7 @@ def test_alternate_tile_fits_lds(V, H, HN, elem):
     assert nbytes(V, H, HN, elem, bx, rr, ALTERNATE) <= LDS_BUDGET
 
 
-@pytest.mark.parametrize("kind", [ALTERNATE, SPLIT])
+@pytest.mark.parametrize("kind", [ALTERNATE, SPLIT, TWIN])
 @pytest.mark.parametrize("V,H,HN", SETS)
 @pytest.mark.parametrize("elem", [8, 4, 2])
 @pytest.mark.parametrize("nx,ny,band_rows", [
@@ -181,7 +190,7 @@ def test_pair_schedule_small(V, H, HN, elem, nx, ny, band_rows, kind):
 
 def test_pair_schedule_benchmark_sizes():
     # the throughput channel and the above-cache channel, D2V37 FP32
-    for kind in (ALTERNATE, SPLIT):
+    for kind in (ALTERNATE, SPLIT, TWIN):
         assert emulate(2048, 512, 37, 3, 3, 4, 0, kind)
         assert emulate(4096, 64, 37, 3, 3, 4, 0, kind)
         grid = grid_of(4096, 2048, *tile_shape(37, 3, 3, 4, kind), 0)
@@ -189,7 +198,7 @@ def test_pair_schedule_benchmark_sizes():
 
 
 def test_every_band_height_at_one_shape():
-    for band_rows, elem, kind in itertools.product(range(1, 30), (4, 2), (ALTERNATE, SPLIT)):
+    for band_rows, elem, kind in itertools.product(range(1, 30), (4, 2), (ALTERNATE, SPLIT, TWIN)):
         emulate(100, 29, 37, 3, 3, elem, band_rows, kind)
 
 
@@ -304,3 +313,125 @@ def test_split_schedule_check_catches_a_wave_counted_early():
 
 def _split_without_group_wait(chunks, rr, HN, a, y0, y1, ny, PW, CW, rng):
     return _run_model(chunks, rr, HN, a, y0, y1, ny, PW, CW, rng, group_wait=False)
+
+
+def twin_schedule_check(chunks, rr, HN, a, y0, y1, ny, PW, CW, rng, late_wait=True,
+                        ring_wait=True):
+    """One random interleaving of the two-producer-group schedule at the level
+    of its LDS counters. Chunk k belongs to producer group k mod 2 as its
+    (k // 2)-th chunk. A producer wave computes its chunk (no ring access),
+    then, for k >= 2, waits for consumed >= CW (k - 1) before it writes the
+    ring rows (late_wait; False moves the wait before the computation, which
+    orders the same accesses), then waits until every wave of its group has
+    counted the group's previous chunk and counts produced[g]. Consumers wait
+    for produced[k mod 2] >= PW (k // 2 + 1). Checks as for the single group:
+    no read of an incomplete or stale row, no write over a row an unfinished
+    reader needs, and every wave reaches the end. ring_wait=False drops the
+    ring wait (a planted mistake the check must catch)."""
+    nring = 2 * rr + 2 * HN
+    need = [min(y0 + (k + 1) * rr + HN, y1 + HN, ny) for k in range(chunks)]
+    rows_of = [list(range(a if k == 0 else need[k - 1], need[k])) for k in range(chunks)]
+    reads_of = []
+    for k in range(chunks):
+        lo, hi = y0 + k * rr, min(y0 + (k + 1) * rr, y1)
+        reads_of.append(sorted({min(max(j - e, 0), ny - 1) for j in range(lo, hi)
+                                for e in range(-HN, HN + 1)}))
+    slot = lambda j: (j - a) % nring  # noqa: E731
+    content, writing, reading = {}, {}, {}
+    produced = [0, 0]
+    consumed = 0
+    # producer wave (g, w) runs chunks g, g + 2, ...; stages: 0 compute,
+    # 1 start writing (ring wait), 2 finish writing, 3 count (group wait)
+    prog = {("p", g, w): [g, 0] for g in range(2) for w in range(PW)}
+    prog.update({("c", 0, w): [0, 0] for w in range(CW)})
+    events = 0
+    while True:
+        ready = []
+        for key, (k, st) in prog.items():
+            if k >= chunks:
+                continue
+            if key[0] == "p":
+                ring_free = k < 2 or consumed >= CW * (k - 1) or not ring_wait
+                if st == 0 and (late_wait or ring_free):
+                    ready.append(key)
+                elif st == 1 and ring_free:
+                    ready.append(key)
+                elif st == 2 or (st == 3 and produced[key[1]] >= PW * (k // 2)):
+                    ready.append(key)
+            else:
+                if st == 0 and produced[k % 2] >= PW * (k // 2 + 1):
+                    ready.append(key)
+                elif st in (1, 2) or (st == 3 and consumed >= CW * k):
+                    ready.append(key)
+        if not ready:
+            break
+        key = ready[rng.integers(len(ready))]
+        k, st = prog[key]
+        events += 1
+        if key[0] == "p":
+            w = (key[1], key[2])
+            if st == 1:                       # start writing chunk k
+                for j in rows_of[k]:
+                    s = slot(j)
+                    for row in reading.get(s, {}).values():
+                        assert row == j, ("overwrite while read", k, j, row)
+                    writing.setdefault(s, set()).add(w)
+                    if content.get(s, (None,))[0] != j:
+                        content[s] = (j, set())
+            elif st == 2:                     # finish writing
+                for j in rows_of[k]:
+                    s = slot(j)
+                    writing[s].discard(w)
+                    content[s][1].add(w)
+            elif st == 3:
+                produced[key[1]] += 1
+            prog[key] = [k + 2, 0] if st == 3 else [k, st + 1]
+        else:
+            w = key[2]
+            if st == 0:                       # start reading chunk k
+                g = k % 2
+                for j in reads_of[k]:
+                    s = slot(j)
+                    row, done = content.get(s, (None, set()))
+                    assert row == j and not writing.get(s), ("stale", k, j)
+                    # every wave of the group that produced row j finished it
+                    src = next(m for m in range(chunks) if j in rows_of[m])
+                    assert {(src % 2, x) for x in range(PW)} <= done, ("incomplete", k, j)
+                    reading.setdefault(s, {})[w] = j
+            elif st == 1:
+                for j in reads_of[k]:
+                    reading[slot(j)].pop(w, None)
+            elif st == 3:
+                consumed += 1
+            prog[key] = [k + 1, 0] if st == 3 else [k, st + 1]
+    assert all(k >= chunks for k, _ in prog.values()), "a wave is stuck"
+    return events
+
+
+@pytest.mark.parametrize("rr,HN,y0,y1,ny,PW,CW", [
+    (3, 3, 5, 10, 24, 3, 2), (3, 3, 0, 64, 512, 4, 3), (3, 3, 64, 128, 512, 4, 3),
+    (2, 4, 3, 17, 17, 2, 1), (3, 3, 20, 24, 24, 4, 3), (4, 4, 0, 40, 40, 3, 2),
+    (3, 3, 509, 512, 512, 4, 3), (3, 3, 0, 2, 2, 4, 3),
+])
+@pytest.mark.parametrize("late_wait", [True, False])
+def test_twin_schedule_random_interleavings(rr, HN, y0, y1, ny, PW, CW, late_wait):
+    rng = np.random.default_rng(rr * 1000 + y0 + late_wait)
+    a = max(y0 - HN, 0)
+    chunks = (y1 - y0 + rr - 1) // rr
+    for _ in range(60):
+        twin_schedule_check(chunks, rr, HN, a, y0, y1, ny, PW, CW, rng, late_wait)
+
+
+def test_twin_schedule_check_catches_a_missing_ring_wait():
+    """The check fails when a producer group writes its chunk without waiting
+    for the consumers to free the ring rows (a planted mistake in the
+    schedule model)."""
+    rng = np.random.default_rng(5)
+    found = False
+    for _ in range(200):
+        try:
+            twin_schedule_check(6, 3, 3, 0, 0, 18, 18, 2, 2, rng, ring_wait=False)
+        except AssertionError:
+            found = True
+            break
+    assert found
