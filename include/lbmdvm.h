@@ -68,7 +68,9 @@ enum lbm_storage {
 /* Population layout in HBM. Both give identical results; the choice only
  * moves the memory traffic. LBM_LAYOUT_AUTO keeps one array stepped in place
  * up to 512 MiB per copy (it stays largely in the 256 MB last-level cache) and
- * two ping-pong copies above that. */
+ * two ping-pong copies above that; 2D problems in LBM_F32 or LBM_F64 whose
+ * velocity set has the two-step kernel (lbm_solver_set_pair_steps) take two
+ * ping-pong copies from 64 MiB per copy, stepped two steps per launch. */
 enum lbm_layout {
     LBM_LAYOUT_AUTO = 0,
     LBM_LAYOUT_IN_PLACE = 1,  /* one array; steps alternate two in-place kinds */

@@ -50,9 +50,27 @@ int64_t face_elems(const lbm_problem_t &p) {
 
 // One population array updated in place (AA pattern) when a copy is at most
 // this size, so that the array can stay largely in the 256 MB last-level cache;
-// two ping-pong copies above it (measured on MI355X: in place is ~7% faster for
-// a 155 MB array, ping-pong ~10% faster for a 1.3 GB one).
+// two ping-pong copies above it (measured on MI355X with one step per launch:
+// in place is ~7% faster for a 155 MB array, ping-pong ~10% faster for a
+// 1.3 GB one).
 constexpr size_t kInPlaceMaxBytes = size_t(512) << 20;
+
+// 2D problems in FP32 deviations or FP64 whose set has the two-step kernel
+// step ping-pong from this size per copy, two steps per launch. Measured on
+// MI355X, us per step in place -> two steps per launch: D2V37 FP32 1024 x 256
+// (39 MB) 12.2 -> 13.8, 2048 x 256 (78 MB) 22.2 -> 19.7, 2048 x 512 43.2 ->
+// 39.2, 2048 x 1024 92.6 -> 67.0; D2V37 FP64 1024 x 256 24.2 -> 21.5, 2048 x
+// 512 94.4 -> 74.5; D2V17 FP32 2048 x 512 20.8 -> 17.6. (FP32 raw storage
+// lost, 43.7 -> 46.2; FP16 deviations and FP32SR keep single steps.)
+constexpr size_t kPairMinBytes = size_t(64) << 20;
+
+bool pair_by_default(const Dvm &d, const lbm_problem_t &p, size_t copy_bytes) {
+    if (p.dim != 2 || copy_bytes < kPairMinBytes) return false;
+    if (p.storage != LBM_F32 && p.storage != LBM_F64) return false;
+    const int id = match_set(d);
+    const Launch *La = id < 0 ? nullptr : find_launch(id, (Storage)p.storage);
+    return La && La->pair;
+}
 
 struct Layout {
     size_t copy_bytes = 0;      // one copy of the populations
@@ -78,7 +96,8 @@ Layout layout_of(const Dvm &d, const lbm_problem_t &p) {
     // problems step ping-pong.
     L.in_place = p.accommodation == 1.0 &&
                  (p.layout == LBM_LAYOUT_IN_PLACE ||
-                  (p.layout == LBM_LAYOUT_AUTO && L.copy_bytes <= kInPlaceMaxBytes));
+                  (p.layout == LBM_LAYOUT_AUTO && L.copy_bytes <= kInPlaceMaxBytes &&
+                   !pair_by_default(d, p, L.copy_bytes)));
     L.pop_bytes = L.in_place ? L.copy_bytes : 2 * L.copy_bytes;
     L.apart_bytes = align_up(sizeof(double) * 4 * std::max(1, d.halo) * face_elems(p));
     L.partial_bytes = align_up(sizeof(double) * 2 * observe_blocks(nodes));

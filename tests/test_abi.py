@@ -137,16 +137,17 @@ def test_layout_choice_sets_copies():
 
 def test_state_bytes_layout():
     d = lbm.Dvm.named("D2V37")
+    one = 37 * 2048 * 512 * 4
     pop, scr = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
                                               storage="f32"))
-    assert pop == 37 * 2048 * 512 * 4
+    assert pop == 2 * one            # two copies, stepped two steps per launch
     assert scr < 1 << 20
     pop16, _ = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
                                               storage="f16dev"))
-    assert pop16 == pop // 2
+    assert pop16 == one // 2         # one array of 2-byte deviations, in place
     pop_sr, _ = lbm.state_bytes(d, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
                                                storage="f32sr"))
-    assert pop_sr == pop             # the same FP32 deviations, collided in FP64
+    assert pop_sr == one             # the same FP32 deviations, collided in FP64, in place
 
 
 def test_unknown_storage_is_refused():
@@ -159,12 +160,22 @@ def test_unknown_storage_is_refused():
 
 def test_state_bytes_in_place_up_to_512_mib_then_two_copies():
     """One population array (stepped in place) while a copy is at most 512 MiB,
-    two copies (ping-pong) above: the 2048 x 512 D2V37 FP32 channel needs one
-    155 MB array, the 128 x 256 x 256 D3V39 FP32 duct two 1.3 GB copies."""
+    two copies (ping-pong) above: the 128 x 256 x 256 D3V39 FP32 duct needs two
+    1.3 GB copies. 2D problems in FP32 deviations or FP64 with a two-step
+    kernel take two copies from 64 MiB per copy: the 1024 x 256 D2V37 FP32
+    channel (39 MB) one array, the 2048 x 256 one (78 MB) two copies, and so
+    the FP64 1024 x 256 one; D2V32 (no two-step kernel) stays in place."""
     d2 = lbm.Dvm.named("D2V37")
-    pop, _ = lbm.state_bytes(d2, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
-                                             storage="f32"))
-    assert pop == 37 * 2048 * 512 * 4
+    for nx, ny, st, size, copies in [(1024, 256, "f32", 4, 1), (2048, 256, "f32", 4, 2),
+                                     (1024, 256, "f64", 8, 2), (1024, 128, "f64", 8, 1),
+                                     (2048, 512, "f16dev", 2, 1), (2048, 512, "f32raw", 4, 1)]:
+        pop, _ = lbm.state_bytes(d2, lbm.Problem(dim=2, nx=nx, ny=ny, kn=0.05, hermite_order=4,
+                                                 storage=st))
+        assert pop == copies * 37 * nx * ny * size, (nx, ny, st)
+    d32 = lbm.Dvm.named("D2V32")
+    pop, _ = lbm.state_bytes(d32, lbm.Problem(dim=2, nx=2048, ny=512, kn=0.05, hermite_order=4,
+                                              storage="f32"))
+    assert pop == 32 * 2048 * 512 * 4
     d3 = lbm.Dvm.named("D3V39")
     one = 39 * 128 * 256 * 256 * 4
     pop3, _ = lbm.state_bytes(d3, lbm.Problem(dim=3, nx=128, ny=256, nz=256, kn=0.1,
