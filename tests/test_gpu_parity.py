@@ -429,17 +429,19 @@ def test_pair_steps_mode_validation():
     assert e.value.code == lbm.LBM_E_UNSUPPORTED
 
 
-def test_pair_steps_full_size_channel():
+@pytest.mark.parametrize("mode", [1, 3])
+def test_pair_steps_full_size_channel(mode):
     """The 2048 x 512 D2V37 FP32 throughput channel stepped ping-pong with two
-    steps per launch (default bands: one per XCD): 10 steps bit-identical to
-    single-step launches, then two more against the oracle over the grid."""
+    steps per launch (default bands; mode 3 is how the library steps this
+    channel by default): 10 steps bit-identical to single-step launches, then
+    two more against the oracle over the grid."""
     c = wl.THROUGHPUT_D2V37
     rho = wl.density_field(c["ny"], c["nx"], seed=c["seed"], amp=c["amp"])
     d, a, o = make_pair(c["dvm"], c["N"], c["nx"], c["ny"], kn=c["kn"], ma=c["ma"],
                         storage="f32", rho=rho, layout="ping_pong")
     _, b, _ = make_pair(c["dvm"], c["N"], c["nx"], c["ny"], kn=c["kn"], ma=c["ma"],
                         storage="f32", rho=rho, layout="ping_pong")
-    a.set_pair_steps(True)
+    a.set_pair_steps(mode)
     b.set_pair_steps(False)
     a.run(10)
     b.run(10)
