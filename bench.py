@@ -29,6 +29,8 @@ sys.path.insert(0, str(ROOT))
 import lbm_workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# the 256 MB last-level cache (Infinity Cache) of one MI355X
+LLC_BYTES = 256 * 2**20
 # the headline's kernel (two steps per launch), the same channel's one-step
 # in-place kernels, and the two-step kernel on the above-cache channel
 HEAD_TRAFFIC_FILE = ROOT / "profiles" / "traffic_pair_d2v37_f32_2048x512.json"
@@ -584,9 +586,11 @@ def scattering_block():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         gbs = 2 * d.V * 4 * nodes / (ms * 1e-3 / c["steps"]) / 1e9
+        pop_bytes = lbm.state_bytes(d, prob)[0]
         out[key] = {"V": d.V, "nodes": nodes, "steps": c["steps"],
                     "mlups": round(nodes * c["steps"] / (ms * 1e-3) / 1e6, 1),
                     "ms_per_step": ms / c["steps"], "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "population_bytes": pop_bytes, "llc_resident": pop_bytes <= LLC_BYTES,
                     "mdot": s.mdot()}
         s.close()
     return out
